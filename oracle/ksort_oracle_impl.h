@@ -1,0 +1,176 @@
+/*
+ * K-sort CPU oracle, type-generic body -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Included twice by ksort_oracle.c, once with KEY_T = double and once with
+ * KEY_T = float; SFX(name) appends the type suffix.  Every function follows
+ * arXiv 1107.3622, Section 1.1, in the paper's own order and names.
+ *
+ * Readings of the text used here (each one is a choice where the text is
+ * silent or self-contradictory):
+ *   R1  Step-2 "repeat Step-3 till (j-i) >= 2 is satisfied" is read as
+ *       "while (j - i >= 2)".  The illustration (Section 1.2, first row)
+ *       needs the comparison made at j - i == 2.
+ *   R2  `flag` is never initialised in Step-1; it is cleared on every
+ *       partition entry.  The third illustration row shows "Temp = Nil".
+ *   R3  Indices are 0-based: the whole array is a[0..n-1].
+ *   R4  Step-5 "sub array from start to i-th element" is [left, i-1] with the
+ *       printed test left < i-1 (at least two elements; the Section 1.2 note
+ *       says a single value needs no processing).
+ *   R5  Step-6 prints "if (left > i+1)", which never holds because i >= left;
+ *       it is read as "if (right > i+1)" on [i+1, right], the mirror of
+ *       Step-5.  The illustration goes on to process the right side.
+ *   R6  Sub-arrays are processed depth-first, left side first, the row order
+ *       of the illustration.  Only the order of trace records depends on it.
+ *   R7  The comparison is exactly `key <= a[p]` in KEY_T: ties go right, and
+ *       a NaN compares false and so goes left.
+ */
+
+/* Steps 1-4: partition a[left..right] around key = a[left]. */
+int64_t SFX(ksort_oracle_partition)(KEY_T *a, int64_t left, int64_t right,
+                                    ksort_oracle_call *rec)
+{
+    /* Step-1: the first element is the key; i = left, j = right + 1,
+     * p = left + 1 and k = p.  flag starts cleared (R2). */
+    KEY_T key = a[left];
+    KEY_T temp = 0;
+    int flag = 0;
+    int64_t i = left;
+    int64_t j = right + 1;
+    int64_t p = left + 1;
+    int64_t k = p;
+    int64_t comparisons = 0;
+
+    /* Step-2: repeat Step-3 while j - i >= 2 (R1). */
+    while (j - i >= 2) {
+        comparisons++;
+        /* Step-3: compare a[p] with the key. */
+        if (key <= a[p]) {
+            /* Step-3.1 */
+            if (p != j && j != right + 1) {
+                a[j] = a[p];
+            } else if (j == right + 1) {
+                temp = a[p];
+                flag = 1;
+            }
+            j = j - 1;
+            p = j;
+        } else {
+            /* Step-3.2 (key > a[p]) */
+            a[i] = a[p];
+            i = i + 1;
+            k = k + 1;
+            p = k;
+        }
+    }
+
+    /* Step-4: the key goes to a[i]; temp, if one was taken, to a[i+1]. */
+    a[i] = key;
+    if (flag == 1)
+        a[i + 1] = temp;
+
+    if (rec) {
+        rec->left = left;
+        rec->right = right;
+        rec->i = i;
+        rec->comparisons = comparisons;
+        rec->k_minus_i = k - i;
+        rec->key = (double)key;
+        rec->temp = flag ? (double)temp : 0.0;
+        rec->flag = flag;
+        rec->pad = 0;
+    }
+    return i;
+}
+
+/* Steps 1-6 on a[0..n-1] with an explicit stack of pending sub-arrays, so
+ * that the worst-case depth (n, for sorted input) cannot overflow the C
+ * stack.  The right side is pushed first so that the left side is popped
+ * first (R6). */
+int SFX(ksort_oracle_sort)(KEY_T *a, int64_t n, int64_t *first_pivot,
+                           ksort_oracle_call *trace, int64_t trace_cap,
+                           int64_t *ncalls, int64_t *ncomparisons)
+{
+    int64_t calls = 0, comps = 0;
+    if (first_pivot)
+        *first_pivot = (n == 0) ? -1 : 0;
+    if (n >= 2) {
+        int64_t cap = 64, top = 0;
+        int64_t *stk = (int64_t *)malloc((size_t)cap * 2 * sizeof(int64_t));
+        if (!stk)
+            return -2;
+        stk[0] = 0;
+        stk[1] = n - 1;
+        top = 1;
+        while (top > 0) {
+            top--;
+            int64_t left = stk[2 * top], right = stk[2 * top + 1];
+            ksort_oracle_call rec;
+            int64_t i = SFX(ksort_oracle_partition)(a, left, right, &rec);
+            if (calls == 0 && first_pivot)
+                *first_pivot = i;
+            if (trace && calls < trace_cap)
+                trace[calls] = rec;
+            calls++;
+            comps += rec.comparisons;
+            if (top + 2 > cap) {
+                int64_t ncap = cap * 2;
+                int64_t *nstk = (int64_t *)realloc(stk, (size_t)ncap * 2 * sizeof(int64_t));
+                if (!nstk) {
+                    free(stk);
+                    return -2;
+                }
+                stk = nstk;
+                cap = ncap;
+            }
+            /* Step-6 (R5): the side right of the key, if it has two or more
+             * elements. */
+            if (right > i + 1) {
+                stk[2 * top] = i + 1;
+                stk[2 * top + 1] = right;
+                top++;
+            }
+            /* Step-5 (R4): the side left of the key, if it has two or more
+             * elements. */
+            if (left < i - 1) {
+                stk[2 * top] = left;
+                stk[2 * top + 1] = i - 1;
+                top++;
+            }
+        }
+        free(stk);
+    }
+    if (ncalls)
+        *ncalls = calls;
+    if (ncomparisons)
+        *ncomparisons = comps;
+    return 0;
+}
+
+/* One application of Steps 1-4 to each listed segment. */
+int SFX(ksort_oracle_partition_level)(KEY_T *a, const int64_t *left,
+                                      const int64_t *len, int64_t nseg,
+                                      int64_t *pivot)
+{
+    for (int64_t s = 0; s < nseg; s++) {
+        if (len[s] < 1)
+            return -1;
+        pivot[s] = SFX(ksort_oracle_partition)(a, left[s], left[s] + len[s] - 1, NULL);
+    }
+    return 0;
+}
+
+/* Steps 1-6 applied to each array of a packed batch on its own. */
+int SFX(ksort_oracle_segmented)(KEY_T *a, const int64_t *offsets, int64_t nseg,
+                                int64_t *first_pivots)
+{
+    for (int64_t s = 0; s < nseg; s++) {
+        int64_t fp = -1;
+        int rc = SFX(ksort_oracle_sort)(a + offsets[s], offsets[s + 1] - offsets[s],
+                                        &fp, NULL, 0, NULL, NULL);
+        if (rc)
+            return rc;
+        if (first_pivots)
+            first_pivots[s] = fp;
+    }
+    return 0;
+}
