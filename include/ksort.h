@@ -1,0 +1,258 @@
+/*
+ * ksort.h -- C ABI of the MI355X (gfx950) K-sort library, libksort.so.
+ *
+ * K-sort (Sundararajan, Pal, Chakraborty, Mahanti, arXiv 1107.3622,
+ * Section 1.1) sorts a[left..right] by taking the first element as the key,
+ * placing every key that is smaller than it to its left and every key that
+ * is larger or equal to its right (Steps 1-4; the key ends at index
+ * i = left + number of smaller keys), and repeating on both sides (Steps 5-6)
+ * until every side has at most one key (Section 1.2 note).  This library
+ * runs each level of that recursion as one pass over all live segments of a
+ * device array.
+ *
+ * Conventions for every entry point below:
+ *   - Arrays named d_* are device memory (hipMalloc, or a torch tensor on the
+ *     HIP device); the caller owns them and keeps them alive until the work
+ *     is complete.  Host pointers are never accepted in a d_* argument.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Keys are IEEE double (KSORT_F64) or float (KSORT_F32), compared in their
+ *     own precision exactly as `key <= x`: ties go right; a NaN compares false
+ *     and goes left.  The sorted order is unique (bit-exact with any correct
+ *     sort) for inputs without NaN and without both +0.0 and -0.0.
+ *   - Sizes are element counts (int64_t).  n = 0 and n = 1 are valid no-ops.
+ *   - Return value: KSORT_OK (0) or a negative KSORT_E* code; nothing is
+ *     thrown across the ABI.  ksort_last_error() gives a thread-local detail
+ *     string for the most recent failure on the calling thread.
+ *   - Completion: the sorting calls return after the work they queued on
+ *     `stream` has finished (the level loop reads a completion flag back from
+ *     the device), so the output may be read as soon as they return.
+ *   - The library keeps one scratch workspace per (device, stream) pair; calls
+ *     on the same stream are serialised, calls on different streams run
+ *     independently.
+ */
+#ifndef KSORT_H
+#define KSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define KSORT_API __attribute__((visibility("default")))
+#else
+#define KSORT_API
+#endif
+
+/* error codes */
+#define KSORT_OK 0
+#define KSORT_EINVAL (-1)      /* bad argument: null pointer with n > 0, n < 0, bad dtype, bad segment */
+#define KSORT_ENOMEM (-2)      /* device or host allocation failed */
+#define KSORT_EHIP (-3)        /* HIP runtime error (detail in ksort_last_error) */
+#define KSORT_EUNSUPPORTED (-4)/* no gfx950 device current */
+#define KSORT_ETOOLARGE (-5)   /* request larger than the server's memory budget */
+#define KSORT_EAGAIN (-6)      /* server queue full */
+#define KSORT_ECANCELLED (-7)  /* request cancelled */
+#define KSORT_ETIMEOUT (-8)    /* wait timed out */
+#define KSORT_ENOTFOUND (-9)   /* unknown server ticket */
+#define KSORT_EINTERNAL (-10)  /* internal capacity check failed (a library bug) */
+
+/* key types */
+#define KSORT_F64 0
+#define KSORT_F32 1
+
+/* Kernel variant: threads per workgroup, keys per thread in a partition tile,
+ * and the finish cutoff (segments of at most `cutoff` keys are sorted inside
+ * one workgroup's LDS).  All-zero fields mean "library default / autotuned".
+ * Only the combinations listed by ksort_variants() exist. */
+typedef struct ksort_tuning {
+    int32_t block;
+    int32_t items;
+    int32_t cutoff;
+    int32_t reserved;
+} ksort_tuning;
+
+/* ------------------------------------------------------------------------
+ * Whole-array sort, Steps 1-6 (Section 1.1).
+ *
+ * ksort_f64 / ksort_f32: sort d_data[0..n-1] ascending, in place.
+ *   d_data : device array of n keys (read and overwritten).
+ *   n      : number of keys, n >= 0.
+ * Scratch: the library uses a device buffer of n keys plus O(n / 2048)
+ * descriptors, cached per (device, stream) and grown on demand.
+ * Errors: KSORT_EINVAL (d_data NULL with n > 0, n < 0), KSORT_ENOMEM,
+ * KSORT_EHIP, KSORT_EUNSUPPORTED.  On error the array content is unspecified
+ * but remains a permutation of the input unless the error is KSORT_EHIP. */
+KSORT_API int ksort_f64(double *d_data, int64_t n, void *stream);
+KSORT_API int ksort_f32(float *d_data, int64_t n, void *stream);
+
+/* ksort_sort_ex: as above with explicit key type and options.
+ *   dtype         : KSORT_F64 or KSORT_F32.
+ *   d_first_pivot : device int64, nullable; receives the index i at which the
+ *                   first partition call (Step-4 on the whole array) left the
+ *                   key a[0]: the number of keys smaller than a[0].  0 for
+ *                   n == 1, -1 for n == 0.
+ *   tune          : nullable; kernel variant to use (NULL = default/tuned). */
+KSORT_API int ksort_sort_ex(int dtype, void *d_data, int64_t n, int64_t *d_first_pivot,
+                  const ksort_tuning *tune, void *stream);
+
+/* ------------------------------------------------------------------------
+ * One partition level, Steps 1-4 (Section 1.1), on many segments at once.
+ *
+ * For every segment s, with left = d_seg_left[s], len = d_seg_len[s] and
+ * right = left + len - 1, the keys d_in[left..right] are written to
+ * d_out[left..right] partitioned around key = d_in[left]:
+ *   d_out[left .. i-1]   the keys smaller than the key (some order),
+ *   d_out[i]             the key, i = left + #{x in (left, right] : key > x},
+ *   d_out[i+1 .. right]  the other keys (some order);
+ * and d_pivot[s] = i (absolute index).  The index i is exactly the one the
+ * paper's Step-4 produces; the order within each side is this library's
+ * (smaller keys in tile order, the others in reverse tile order), not the
+ * order Steps 2-3 leave.
+ *   d_in, d_out : device arrays of n keys; they must not overlap.  Elements
+ *                 of d_out outside every segment are not written.
+ *   d_seg_left, d_seg_len : device int64 arrays of nseg entries; segments
+ *                 must be disjoint, 1 <= len and left + len <= n.
+ *   d_pivot     : device int64 array of nseg entries (output).
+ * Errors: KSORT_EINVAL for a bad dtype/pointer/size or any segment outside
+ * [0, n) or with len < 1 (such segments are skipped; the others are done).
+ * Overlapping segments give unspecified results. */
+KSORT_API int ksort_partition_level(int dtype, const void *d_in, void *d_out, int64_t n,
+                          const int64_t *d_seg_left, const int64_t *d_seg_len,
+                          int64_t nseg, int64_t *d_pivot, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched sort: Steps 1-6 on each array of a packed batch.
+ *
+ * Array u is d_packed[d_offsets[u] .. d_offsets[u+1]-1]; each is sorted on
+ * its own, in place, all of them in one sequence of level passes.
+ *   d_packed        : device array of n_total keys.
+ *   d_offsets       : device int64 array of nseg + 1 non-decreasing offsets,
+ *                     d_offsets[0] >= 0 and d_offsets[nseg] <= n_total.
+ *   d_first_pivots  : device int64 array of nseg entries, nullable; entry u
+ *                     receives the first partition's index i relative to the
+ *                     array start (0 for one key, -1 for an empty array).
+ *   tune            : nullable kernel variant.
+ * The level sequence is recorded once per (stream, sizes, pointers) as a HIP
+ * graph and replayed on later calls with the same arguments.
+ * Errors: KSORT_EINVAL for bad pointers/sizes or offsets that break the rules
+ * above (arrays that do are skipped; the others are sorted). */
+KSORT_API int ksort_segmented(int dtype, void *d_packed, int64_t n_total,
+                    const int64_t *d_offsets, int64_t nseg,
+                    int64_t *d_first_pivots, const ksort_tuning *tune,
+                    void *stream);
+
+/* ------------------------------------------------------------------------
+ * Variants, tuning and profiling (library services, not paper passages).
+ *
+ * ksort_variants: writes up to `cap` compiled variants for `dtype` to `out`
+ *   (host array) and returns how many exist (or a negative error).
+ * ksort_get_default / ksort_set_default: the variant used when `tune` is
+ *   NULL, per key type (host struct).
+ * ksort_autotune: times every variant on a seeded input of n keys on the
+ *   current device and stores the fastest as the default for inputs of about
+ *   that size; `out` (host, nullable) receives it.  Uses a temporary device
+ *   buffer of 2n keys.
+ * ksort_profile_enable(1) makes every level pass record HIP events on its
+ *   stream; ksort_profile_read copies up to `cap` records (host array) and
+ *   clears them; ksort_profile_count returns how many are held. */
+typedef struct ksort_level_record {
+    int64_t call;         /* sequence number of the sorting call */
+    int32_t dtype;
+    int32_t stage;        /* level index within the call (0 = whole arrays) */
+    int64_t live_keys;    /* keys partitioned in this pass */
+    int64_t finish_keys;  /* keys sorted by the LDS finish in this pass */
+    double ms;            /* pass duration from HIP events */
+    int32_t block, items, cutoff, grid;
+} ksort_level_record;
+
+KSORT_API int ksort_variants(int dtype, ksort_tuning *out, int cap);
+KSORT_API int ksort_get_default(int dtype, ksort_tuning *out);
+KSORT_API int ksort_set_default(int dtype, const ksort_tuning *tune);
+KSORT_API int ksort_autotune(int dtype, int64_t n, ksort_tuning *out, void *stream);
+KSORT_API int ksort_profile_enable(int on);
+KSORT_API int64_t ksort_profile_count(void);
+KSORT_API int64_t ksort_profile_read(ksort_level_record *out, int64_t cap);
+
+/* Bytes of device scratch a sort of n keys in nseg arrays needs (host only,
+ * no device call). */
+KSORT_API size_t ksort_workspace_bytes(int dtype, int64_t n, int64_t nseg);
+
+/* Releases every cached workspace of the calling process (all devices). */
+KSORT_API int ksort_release_workspaces(void);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * A server owns a scheduler thread on one device.  Each submitted request
+ * is a device array to sort in place.  Requests are admitted while the sum
+ * of their footprints (2 * n * sizeof(key) for data plus ping-pong scratch,
+ * plus descriptors) stays within `hbm_budget_bytes` and fewer than
+ * `max_inflight` are admitted; every scheduler tick runs one level pass over
+ * the live segments of all admitted requests together (one pass per key
+ * type), so requests that arrive while others are running join at the next
+ * level boundary.  The comparisons and the key rule are those of the plain
+ * sort, so each request's output is identical to ksort_f64/ksort_f32 on the
+ * same array.
+ *
+ * ksort_server_create: device = HIP device ordinal.  Returns NULL on error
+ *   (see ksort_last_error).
+ * ksort_server_submit: d_data is borrowed until the request completes or is
+ *   cancelled; *ticket receives its id.  KSORT_ETOOLARGE if the request can
+ *   never fit the budget, KSORT_EAGAIN if the pending queue is full.
+ * ksort_server_poll: *state = 0 pending/running, 1 done, or a negative error.
+ * ksort_server_wait: blocks up to timeout_s seconds (negative = forever);
+ *   returns KSORT_OK when done, KSORT_ETIMEOUT, or the request's error.
+ * ksort_server_cancel: a request not yet admitted is dropped
+ *   (KSORT_ECANCELLED is then its state); an admitted one runs to completion.
+ * ksort_server_result: first pivot (relative index) and timings of a done
+ *   request.
+ * ksort_server_stats: aggregate counters and latency percentiles.
+ * ksort_server_destroy: stops admitting, lets admitted requests finish,
+ *   cancels queued ones, joins the thread and frees the server. */
+typedef struct ksort_server ksort_server;
+
+typedef struct ksort_request_info {
+    int64_t n;
+    int32_t dtype;
+    int32_t state;          /* as ksort_server_poll */
+    int64_t first_pivot;
+    double t_submit_s;      /* host steady clock, seconds */
+    double t_admit_s;
+    double t_done_s;
+    int32_t levels;         /* level passes the request took part in */
+    int32_t pad;
+} ksort_request_info;
+
+typedef struct ksort_server_stats_t {
+    int64_t submitted, admitted, completed, rejected, cancelled, failed;
+    int64_t keys_completed;
+    int64_t ticks;
+    double busy_s;          /* wall time with at least one admitted request */
+    double p50_latency_s, p99_latency_s, mean_latency_s;
+    int64_t inflight_now, queued_now;
+    int64_t budget_used_bytes;
+} ksort_server_stats_t;
+
+KSORT_API ksort_server *ksort_server_create(size_t hbm_budget_bytes, int max_inflight, int device);
+KSORT_API int ksort_server_submit(ksort_server *srv, int dtype, void *d_data, int64_t n, uint64_t *ticket);
+KSORT_API int ksort_server_poll(ksort_server *srv, uint64_t ticket, int *state);
+KSORT_API int ksort_server_wait(ksort_server *srv, uint64_t ticket, double timeout_s);
+KSORT_API int ksort_server_cancel(ksort_server *srv, uint64_t ticket);
+KSORT_API int ksort_server_result(ksort_server *srv, uint64_t ticket, ksort_request_info *out);
+KSORT_API int ksort_server_stats(ksort_server *srv, ksort_server_stats_t *out);
+KSORT_API void ksort_server_destroy(ksort_server *srv);
+
+/* ------------------------------------------------------------------------ */
+KSORT_API const char *ksort_strerror(int code);
+KSORT_API const char *ksort_last_error(void);
+/* Library version string. */
+KSORT_API const char *ksort_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KSORT_H */

@@ -1,0 +1,115 @@
+// Host-side level driver of the K-sort library (internal C++ interface,
+// shared by the C ABI in ksort_lib.hip and the server in ksort_server.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ksort.h"
+#include "ksort_types.h"
+
+namespace ksort {
+
+// thread-local error detail
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define KSORT_HIP(call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+  } while (0)
+
+// A compiled kernel variant.
+struct Variant {
+  int dtype;
+  int block, items, cutoff;
+  const void* stage;      // stage_kernel<T, BLOCK, ITEMS, CUT>
+  size_t key_bytes;
+  int tile() const { return block * items; }
+};
+
+const std::vector<Variant>& variants();
+// Explicit `tune` if given; otherwise the autotuned variant for inputs of
+// about n keys, else the default for the key type.
+const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n = -1);
+bool tuned_for(int dtype, int64_t n, ksort_tuning* out);
+int set_default_variant(int dtype, const ksort_tuning* tune);
+
+struct DeviceInfo {
+  int ordinal = -1;
+  int cus = 0;
+  bool gfx950 = false;
+  std::string arch;
+  std::vector<int> occupancy;  // blocks per CU, indexed like variants()
+};
+int device_info(int ordinal, const DeviceInfo** out);
+
+// Capacities of the descriptor lists for one run.
+struct Caps {
+  int64_t live = 0, tiles = 0, fin = 0, bufs = 1;
+};
+Caps caps_for(const Variant& v, int64_t n, int64_t nseg, bool level_mode);
+
+// Device workspace: descriptor lists, counters, flags, look-back words and
+// the ping-pong scratch.  One per (device, stream) for the C ABI calls; the
+// server owns its own.
+struct Workspace {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  Caps caps;
+  int cap_stats = 256;
+  StageCtr* ctr = nullptr;
+  Flags* flags = nullptr;
+  Seg* live[2] = {nullptr, nullptr};
+  int32_t* tilemap[2] = {nullptr, nullptr};
+  Seg* fin[2] = {nullptr, nullptr};
+  uint64_t* status = nullptr;
+  BufPair* bufs = nullptr;
+  int64_t* stage_keys = nullptr;
+  int32_t* pending = nullptr;
+  int32_t* done_stage = nullptr;
+  uint32_t epoch = 0;         // last epoch used
+  Flags* h_flags = nullptr;   // pinned readback
+  std::mutex mu;
+  ~Workspace();
+  // make room for a run; scratch_keys * key_bytes bytes of scratch
+  int reserve(const Caps& c, size_t scratch_bytes_needed);
+  uint32_t next_epoch();      // clears the look-back words when the tag wraps
+};
+
+Workspace* workspace_for(int device, hipStream_t stream);
+void release_workspaces();
+
+// Arguments of one stage launch built from a workspace.
+StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_out, int pivot_relative,
+                     int emit_children);
+
+// Launch helpers (asynchronous on ws.stream).
+int launch_reset(Workspace& ws);
+int launch_init(Workspace& ws, const Variant& v, const InitArgs& ia, int64_t nblocks);
+int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid);
+int stage_grid(const Variant& v, const DeviceInfo& di, const Caps& c);
+
+// Predicted number of level passes for n keys (used to size launch batches).
+int predict_stages(int64_t n, int cutoff);
+
+// Whole sort of one packed buffer (single array when offsets == nullptr).
+int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64_t nseg,
+             int64_t* d_pivots, const ksort_tuning* tune, hipStream_t stream, bool use_graph);
+
+// Profiling records
+bool profiling_on();
+void profile_push(const ksort_level_record& r);
+int64_t next_call_id();
+
+}  // namespace ksort

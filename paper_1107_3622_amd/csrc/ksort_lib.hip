@@ -1,0 +1,711 @@
+// K-sort library for MI355X (gfx950): host level driver and C ABI.
+//
+// A sort runs as a sequence of stage launches.  Stage 0 holds the input
+// arrays; stage s partitions every live segment once (Steps 1-4 of
+// arXiv 1107.3622, Section 1.1) and finishes in LDS every segment of at most
+// `cutoff` keys that stage s-1 produced; its two sides (Steps 5-6) become the
+// segments of stage s+1.  The device keeps all lists and counters, so the host
+// only launches stages in batches and reads one flag word after each batch to
+// learn whether work is left.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ksort.h"
+#include "ksort_engine.h"
+#include "ksort_kernels.h"
+
+namespace ksort {
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string t_last_error;
+
+void set_error(const std::string& msg) { t_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  char buf[512];
+  snprintf(buf, sizeof buf, "%s failed: %s (%d)", what, hipGetErrorString(e), (int)e);
+  set_error(buf);
+  return e == hipErrorOutOfMemory ? KSORT_ENOMEM : KSORT_EHIP;
+}
+
+// ---------------------------------------------------------------- variants
+
+template <typename T, int BLOCK, int ITEMS, int CUT>
+static Variant make_variant(int dtype) {
+  Variant v;
+  v.dtype = dtype;
+  v.block = BLOCK;
+  v.items = ITEMS;
+  v.cutoff = CUT;
+  v.stage = (const void*)&stage_kernel<T, BLOCK, ITEMS, CUT>;
+  v.key_bytes = sizeof(T);
+  return v;
+}
+
+const std::vector<Variant>& variants() {
+  static const std::vector<Variant> vs = {
+      make_variant<double, 256, 16, 2048>(KSORT_F64),
+      make_variant<double, 256, 8, 2048>(KSORT_F64),
+      make_variant<double, 512, 8, 2048>(KSORT_F64),
+      make_variant<double, 256, 16, 1024>(KSORT_F64),
+      make_variant<float, 256, 16, 2048>(KSORT_F32),
+      make_variant<float, 256, 8, 2048>(KSORT_F32),
+      make_variant<float, 512, 8, 2048>(KSORT_F32),
+      make_variant<float, 256, 16, 1024>(KSORT_F32),
+  };
+  return vs;
+}
+
+static std::mutex g_default_mu;
+static int g_default[2] = {-1, -1};
+
+static int variant_index(int dtype, int block, int items, int cutoff) {
+  const auto& vs = variants();
+  for (size_t j = 0; j < vs.size(); ++j)
+    if (vs[j].dtype == dtype && vs[j].block == block && vs[j].items == items && vs[j].cutoff == cutoff)
+      return (int)j;
+  return -1;
+}
+
+const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n) {
+  if (dtype != KSORT_F64 && dtype != KSORT_F32) return nullptr;
+  const auto& vs = variants();
+  if (tune && (tune->block || tune->items || tune->cutoff)) {
+    const int j = variant_index(dtype, tune->block, tune->items, tune->cutoff);
+    return j < 0 ? nullptr : &vs[j];
+  }
+  ksort_tuning tn;
+  if (n >= 0 && tuned_for(dtype, n, &tn)) {
+    const int j = variant_index(dtype, tn.block, tn.items, tn.cutoff);
+    if (j >= 0) return &vs[j];
+  }
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  int j = g_default[dtype];
+  if (j < 0) j = variant_index(dtype, 256, 16, 2048);
+  return &vs[j];
+}
+
+int set_default_variant(int dtype, const ksort_tuning* tune) {
+  if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
+  int j = -1;
+  if (tune) {
+    j = variant_index(dtype, tune->block, tune->items, tune->cutoff);
+    if (j < 0) return fail(KSORT_EINVAL, "no such kernel variant");
+  }
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  g_default[dtype] = j;
+  return KSORT_OK;
+}
+
+// ---------------------------------------------------------------- device info
+
+static std::mutex g_dev_mu;
+static std::map<int, std::unique_ptr<DeviceInfo>> g_devs;
+
+int device_info(int ordinal, const DeviceInfo** out) {
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_devs.find(ordinal);
+  if (it != g_devs.end()) {
+    *out = it->second.get();
+    return KSORT_OK;
+  }
+  hipDeviceProp_t prop;
+  KSORT_HIP(hipGetDeviceProperties(&prop, ordinal));
+  auto di = std::make_unique<DeviceInfo>();
+  di->ordinal = ordinal;
+  di->cus = prop.multiProcessorCount;
+  di->arch = prop.gcnArchName;
+  di->gfx950 = di->arch.rfind("gfx950", 0) == 0;
+  for (const auto& v : variants()) {
+    int nb = 0;
+    KSORT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v.stage, v.block, 0));
+    di->occupancy.push_back(std::max(nb, 1));
+  }
+  *out = di.get();
+  g_devs[ordinal] = std::move(di);
+  return KSORT_OK;
+}
+
+// ---------------------------------------------------------------- capacities
+
+Caps caps_for(const Variant& v, int64_t n, int64_t nseg, bool level_mode) {
+  Caps c;
+  if (level_mode) {
+    c.live = nseg + 2;
+    c.tiles = n / v.tile() + nseg + 2;
+    c.fin = 2;
+  } else {
+    // live segments have more than `cutoff` keys and are disjoint
+    c.live = n / (v.cutoff + 1) + 2;
+    c.tiles = n / v.tile() + c.live + 2;
+    // stage 0 may hold every small input array; later stages at most two
+    // sides per live segment of the stage before
+    c.fin = std::max<int64_t>(nseg, 2 * c.live) + 2;
+  }
+  return c;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t arena_bytes_for(const Caps& c, int cap_stats) {
+  size_t b = 0;
+  b += align256(3 * sizeof(StageCtr));
+  b += align256(sizeof(Flags));
+  b += 2 * align256((size_t)c.live * sizeof(Seg));
+  b += 2 * align256((size_t)c.tiles * sizeof(int32_t));
+  b += 2 * align256((size_t)c.fin * sizeof(Seg));
+  b += align256((size_t)c.tiles * sizeof(uint64_t));
+  b += align256((size_t)c.bufs * sizeof(BufPair));
+  b += align256((size_t)cap_stats * 2 * sizeof(int64_t));
+  b += 2 * align256((size_t)c.bufs * sizeof(int32_t));
+  return b;
+}
+
+Workspace::~Workspace() {
+  if (arena) (void)hipFree(arena);
+  if (scratch) (void)hipFree(scratch);
+  if (h_flags) (void)hipHostFree(h_flags);
+}
+
+int Workspace::reserve(const Caps& c, size_t scratch_need) {
+  if (!h_flags) KSORT_HIP(hipHostMalloc((void**)&h_flags, sizeof(Flags), hipHostMallocDefault));
+  const bool fits = c.live <= caps.live && c.tiles <= caps.tiles && c.fin <= caps.fin && c.bufs <= caps.bufs;
+  if (!arena || !fits) {
+    Caps nc;
+    nc.live = std::max(c.live, caps.live);
+    nc.tiles = std::max(c.tiles, caps.tiles);
+    nc.fin = std::max(c.fin, caps.fin);
+    nc.bufs = std::max(c.bufs, caps.bufs);
+    if (arena) {
+      KSORT_HIP(hipStreamSynchronize(stream));
+      KSORT_HIP(hipFree(arena));
+      arena = nullptr;
+    }
+    const size_t bytes = arena_bytes_for(nc, cap_stats);
+    KSORT_HIP(hipMalloc(&arena, bytes));
+    arena_bytes = bytes;
+    caps = nc;
+    char* p = (char*)arena;
+    auto take = [&](size_t sz) {
+      char* r = p;
+      p += align256(sz);
+      return (void*)r;
+    };
+    ctr = (StageCtr*)take(3 * sizeof(StageCtr));
+    flags = (Flags*)take(sizeof(Flags));
+    for (int k = 0; k < 2; ++k) live[k] = (Seg*)take((size_t)nc.live * sizeof(Seg));
+    for (int k = 0; k < 2; ++k) tilemap[k] = (int32_t*)take((size_t)nc.tiles * sizeof(int32_t));
+    for (int k = 0; k < 2; ++k) fin[k] = (Seg*)take((size_t)nc.fin * sizeof(Seg));
+    status = (uint64_t*)take((size_t)nc.tiles * sizeof(uint64_t));
+    bufs = (BufPair*)take((size_t)nc.bufs * sizeof(BufPair));
+    stage_keys = (int64_t*)take((size_t)cap_stats * 2 * sizeof(int64_t));
+    pending = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
+    done_stage = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
+    KSORT_HIP(hipMemsetAsync(arena, 0, bytes, stream));
+    epoch = 0;
+  }
+  if (scratch_need > scratch_bytes) {
+    if (scratch) {
+      KSORT_HIP(hipStreamSynchronize(stream));
+      KSORT_HIP(hipFree(scratch));
+      scratch = nullptr;
+      scratch_bytes = 0;
+    }
+    KSORT_HIP(hipMalloc(&scratch, scratch_need));
+    scratch_bytes = scratch_need;
+  }
+  return KSORT_OK;
+}
+
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+
+Workspace* workspace_for(int device, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  auto key = std::make_pair(device, stream);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) return it->second.get();
+  auto ws = std::make_unique<Workspace>();
+  ws->device = device;
+  ws->stream = stream;
+  Workspace* r = ws.get();
+  g_ws[key] = std::move(ws);
+  return r;
+}
+
+void release_workspaces() {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  g_ws.clear();
+}
+
+// ---------------------------------------------------------------- launches
+
+constexpr uint32_t kEpochSpan = (1u << 22) - 1;  // epochs 1 .. 2^22-1
+
+static uint32_t epoch_of(int stage) { return (uint32_t)(stage % kEpochSpan) + 1; }
+
+StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_out, int pivot_relative,
+                     int emit_children) {
+  StageArgs a;
+  memset(&a, 0, sizeof a);
+  a.ctr = ws.ctr;
+  for (int k = 0; k < 2; ++k) {
+    a.live[k] = ws.live[k];
+    a.tilemap[k] = ws.tilemap[k];
+    a.fin[k] = ws.fin[k];
+  }
+  a.status = ws.status;
+  a.bufs = ws.bufs;
+  a.pivot_out = pivot_out;
+  a.pending = nullptr;
+  a.done_stage = nullptr;
+  a.flags = ws.flags;
+  a.stage_keys = ws.stage_keys;
+  a.cap_live = (int32_t)ws.caps.live;
+  a.cap_tiles = (int32_t)ws.caps.tiles;
+  a.cap_fin = (int32_t)ws.caps.fin;
+  a.cap_stats = ws.cap_stats;
+  a.stage = stage;
+  a.epoch = epoch_of(stage);
+  a.cutoff = v.cutoff;
+  a.emit_children = emit_children;
+  a.pivot_relative = pivot_relative;
+  return a;
+}
+
+int launch_reset(Workspace& ws) {
+  const int64_t nwords = ws.caps.tiles;
+  const int blocks = (int)std::min<int64_t>(1024, (nwords + 255) / 256);
+  hipLaunchKernelGGL(clear_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, ws.stream, ws.status, nwords);
+  KSORT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, ws.stream, ws.ctr, ws.flags, ws.stage_keys, ws.cap_stats);
+  KSORT_HIP(hipGetLastError());
+  return KSORT_OK;
+}
+
+int launch_init(Workspace& ws, const Variant& v, const InitArgs& ia, int64_t nblocks) {
+  (void)v;
+  if (nblocks <= 0) return KSORT_OK;
+  if (nblocks > 0x7fffffff) return fail(KSORT_EINVAL, "too many arrays");
+  hipLaunchKernelGGL(init_kernel, dim3((uint32_t)nblocks), dim3(256), 0, ws.stream, ia);
+  KSORT_HIP(hipGetLastError());
+  return KSORT_OK;
+}
+
+int stage_grid(const Variant& v, const DeviceInfo& di, const Caps& c) {
+  const auto& vs = variants();
+  const int idx = (int)(&v - vs.data());
+  const int64_t full = (int64_t)di.occupancy[idx] * di.cus;
+  const int64_t work = c.tiles + c.fin;
+  return (int)std::max<int64_t>(1, std::min(full, work));
+}
+
+int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid) {
+  StageArgs args = a;
+  void* params[] = {&args};
+  KSORT_HIP(hipLaunchKernel(v.stage, dim3(grid), dim3(v.block), params, 0, ws.stream));
+  return KSORT_OK;
+}
+
+int predict_stages(int64_t n, int cutoff) {
+  if (n <= cutoff) return 1;
+  const double r = std::log2((double)n / (double)cutoff);
+  return (int)std::ceil(2.7 * r) + 3;
+}
+
+// ---------------------------------------------------------------- profiling
+
+static std::atomic<int> g_profile{0};
+static std::mutex g_prof_mu;
+static std::vector<ksort_level_record> g_prof;
+static std::atomic<int64_t> g_call{0};
+
+bool profiling_on() { return g_profile.load() != 0; }
+void profile_push(const ksort_level_record& r) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.push_back(r);
+}
+int64_t next_call_id() { return g_call.fetch_add(1); }
+
+// ---------------------------------------------------------------- graphs
+
+struct GraphKey {
+  int dtype;
+  void* data;
+  int64_t n;
+  const int64_t* offsets;
+  int64_t nseg;
+  int64_t* pivots;
+  const Variant* v;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(dtype, data, n, offsets, nseg, pivots, v) <
+           std::tie(o.dtype, o.data, o.n, o.offsets, o.nseg, o.pivots, o.v);
+  }
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  int stages = 0;
+  void* arena = nullptr;    // workspace buffers the graph was recorded with
+  void* scratch = nullptr;
+};
+
+static std::mutex g_graph_mu;
+static std::map<std::pair<Workspace*, GraphKey>, GraphEntry> g_graphs;
+
+// ---------------------------------------------------------------- the sort
+
+static int enqueue_prologue(Workspace& ws, const Variant& v, int dtype, void* d_data, int64_t n,
+                            const int64_t* d_offsets, int64_t nseg, int64_t* d_pivots) {
+  (void)dtype;
+  int rc = launch_reset(ws);
+  if (rc) return rc;
+  InitArgs ia;
+  memset(&ia, 0, sizeof ia);
+  ia.sa = stage_args(ws, v, 0, d_pivots, 1, 1);
+  ia.pair.data = d_data;
+  ia.pair.scratch = ws.scratch;
+  ia.buf = 0;
+  ia.root_base = 0;
+  ia.n = n;
+  ia.offsets = d_offsets;
+  ia.seg_left = nullptr;
+  ia.seg_len = nullptr;
+  ia.nseg = nseg;
+  ia.level_mode = 0;
+  ia.tile = v.tile();
+  return launch_init(ws, v, ia, nseg);
+}
+
+int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64_t nseg, int64_t* d_pivots,
+             const ksort_tuning* tune, hipStream_t stream, bool use_graph) {
+  if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
+  if (n < 0 || nseg < 0) return fail(KSORT_EINVAL, "negative size");
+  if (n > 0 && !d_data) return fail(KSORT_EINVAL, "null data pointer");
+  if (d_offsets == nullptr && nseg != 1) return fail(KSORT_EINVAL, "internal: single array needs nseg == 1");
+  if (n > ((int64_t)1 << 31) - 1) return fail(KSORT_EINVAL, "more than 2^31-1 keys");
+  const Variant* v = find_variant(dtype, tune, n);
+  if (!v) return fail(KSORT_EINVAL, "no such kernel variant");
+  if (nseg == 0) return KSORT_OK;
+  if (d_offsets == nullptr && n <= 1) {
+    if (d_pivots) {
+      const int64_t fp = n == 0 ? -1 : 0;
+      KSORT_HIP(hipMemcpyAsync(d_pivots, &fp, sizeof fp, hipMemcpyHostToDevice, stream));
+      KSORT_HIP(hipStreamSynchronize(stream));
+    }
+    return KSORT_OK;
+  }
+  int dev = 0;
+  KSORT_HIP(hipGetDevice(&dev));
+  const DeviceInfo* di = nullptr;
+  int rc = device_info(dev, &di);
+  if (rc) return rc;
+  if (!di->gfx950) return fail(KSORT_EUNSUPPORTED, "device " + std::to_string(dev) + " is " + di->arch + ", not gfx950");
+
+  Workspace& ws = *workspace_for(dev, stream);
+  std::lock_guard<std::mutex> lk(ws.mu);
+  const Caps caps = caps_for(*v, n, nseg, false);
+  rc = ws.reserve(caps, (size_t)std::max<int64_t>(n, 1) * v->key_bytes);
+  if (rc) return rc;
+  const int grid = stage_grid(*v, *di, ws.caps);
+  const bool prof = profiling_on();
+  const int64_t call = next_call_id();
+
+  int stage = 0;
+  int batch = predict_stages(n, v->cutoff);
+  bool graphed = false;
+
+  if (use_graph && !prof) {
+    GraphKey key{dtype, d_data, n, d_offsets, nseg, d_pivots, v};
+    std::lock_guard<std::mutex> gl(g_graph_mu);
+    auto gk = std::make_pair(&ws, key);
+    auto it = g_graphs.find(gk);
+    if (it != g_graphs.end() && (it->second.arena != ws.arena || it->second.scratch != ws.scratch)) {
+      (void)hipGraphExecDestroy(it->second.exec);
+      g_graphs.erase(it);
+      it = g_graphs.end();
+    }
+    if (it == g_graphs.end()) {
+      hipGraph_t g = nullptr;
+      KSORT_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      int crc = enqueue_prologue(ws, *v, dtype, d_data, n, d_offsets, nseg, d_pivots);
+      for (int s = 0; s < batch && crc == KSORT_OK; ++s)
+        crc = launch_stage(ws, *v, stage_args(ws, *v, s, d_pivots, 1, 1), grid);
+      if (crc == KSORT_OK) {
+        hipError_t e = hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, stream);
+        if (e != hipSuccess) crc = hip_fail(e, "hipMemcpyAsync(flags)");
+      }
+      hipError_t e = hipStreamEndCapture(stream, &g);
+      if (crc) {
+        if (g) (void)hipGraphDestroy(g);
+        return crc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+      GraphEntry ge;
+      e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+      ge.stages = batch;
+      ge.arena = ws.arena;
+      ge.scratch = ws.scratch;
+      it = g_graphs.emplace(gk, ge).first;
+    }
+    KSORT_HIP(hipGraphLaunch(it->second.exec, stream));
+    KSORT_HIP(hipStreamSynchronize(stream));
+    stage = it->second.stages;
+    graphed = true;
+  } else {
+    rc = enqueue_prologue(ws, *v, dtype, d_data, n, d_offsets, nseg, d_pivots);
+    if (rc) return rc;
+  }
+
+  std::vector<hipEvent_t> evs;
+  std::vector<int> ev_stage;
+  for (;;) {
+    if (graphed) {
+      graphed = false;  // flags were read back by the graph
+    } else {
+      for (int b = 0; b < batch; ++b, ++stage) {
+        if (stage > 0 && stage % (int)kEpochSpan == 0) {
+          const int64_t nwords = ws.caps.tiles;
+          hipLaunchKernelGGL(clear_kernel, dim3(256), dim3(256), 0, ws.stream, ws.status, nwords);
+          KSORT_HIP(hipGetLastError());
+        }
+        if (prof) {
+          hipEvent_t e0, e1;
+          KSORT_HIP(hipEventCreate(&e0));
+          KSORT_HIP(hipEventCreate(&e1));
+          KSORT_HIP(hipEventRecord(e0, stream));
+          rc = launch_stage(ws, *v, stage_args(ws, *v, stage, d_pivots, 1, 1), grid);
+          KSORT_HIP(hipEventRecord(e1, stream));
+          evs.push_back(e0);
+          evs.push_back(e1);
+          ev_stage.push_back(stage);
+        } else {
+          rc = launch_stage(ws, *v, stage_args(ws, *v, stage, d_pivots, 1, 1), grid);
+        }
+        if (rc) return rc;
+      }
+      KSORT_HIP(hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, stream));
+      KSORT_HIP(hipStreamSynchronize(stream));
+    }
+    const Flags f = *ws.h_flags;
+    if (f.overflow) return fail(KSORT_EINTERNAL, "device consistency check failed (code " + std::to_string(f.overflow) + ")");
+    if (f.last_active < stage) {
+      if (f.err) return fail(KSORT_EINVAL, "an array offset is outside [0, n_total] or decreasing");
+      break;
+    }
+    // every level pass finishes at least one key per live segment
+    if (stage > n + 64) return fail(KSORT_EINTERNAL, "level loop did not terminate");
+    batch = std::min(64, std::max(8, stage / 4));
+  }
+
+  if (prof) {
+    std::vector<int64_t> sk((size_t)ws.cap_stats * 2);
+    KSORT_HIP(hipMemcpy(sk.data(), ws.stage_keys, sk.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < ev_stage.size(); ++k) {
+      float ms = 0.f;
+      KSORT_HIP(hipEventElapsedTime(&ms, evs[2 * k], evs[2 * k + 1]));
+      ksort_level_record r;
+      memset(&r, 0, sizeof r);
+      r.call = call;
+      r.dtype = dtype;
+      r.stage = ev_stage[k];
+      r.live_keys = ev_stage[k] < ws.cap_stats ? sk[2 * ev_stage[k]] : -1;
+      r.finish_keys = ev_stage[k] < ws.cap_stats ? sk[2 * ev_stage[k] + 1] : -1;
+      r.ms = ms;
+      r.block = v->block;
+      r.items = v->items;
+      r.cutoff = v->cutoff;
+      r.grid = grid;
+      profile_push(r);
+    }
+    for (auto e : evs) (void)hipEventDestroy(e);
+  }
+  return KSORT_OK;
+}
+
+static int run_level(int dtype, const void* d_in, void* d_out, int64_t n, const int64_t* d_left,
+                     const int64_t* d_len, int64_t nseg, int64_t* d_pivot, hipStream_t stream) {
+  if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
+  if (n < 0 || nseg < 0) return fail(KSORT_EINVAL, "negative size");
+  if (nseg == 0) return KSORT_OK;
+  if (!d_in || !d_out || !d_left || !d_len || !d_pivot) return fail(KSORT_EINVAL, "null pointer");
+  if (d_in == d_out) return fail(KSORT_EINVAL, "d_in and d_out must not overlap");
+  if (nseg > 0x7ffffff0) return fail(KSORT_EINVAL, "too many segments");
+  const Variant* v = find_variant(dtype, nullptr);
+  int dev = 0;
+  KSORT_HIP(hipGetDevice(&dev));
+  const DeviceInfo* di = nullptr;
+  int rc = device_info(dev, &di);
+  if (rc) return rc;
+  if (!di->gfx950) return fail(KSORT_EUNSUPPORTED, "device is " + di->arch + ", not gfx950");
+  Workspace& ws = *workspace_for(dev, stream);
+  std::lock_guard<std::mutex> lk(ws.mu);
+  const Caps caps = caps_for(*v, n, nseg, true);
+  rc = ws.reserve(caps, 0);
+  if (rc) return rc;
+  rc = launch_reset(ws);
+  if (rc) return rc;
+  InitArgs ia;
+  memset(&ia, 0, sizeof ia);
+  ia.sa = stage_args(ws, *v, 0, d_pivot, 0, 0);
+  ia.pair.data = d_out;
+  ia.pair.scratch = const_cast<void*>(d_in);
+  ia.buf = 0;
+  ia.root_base = 0;
+  ia.n = n;
+  ia.offsets = nullptr;
+  ia.seg_left = d_left;
+  ia.seg_len = d_len;
+  ia.nseg = nseg;
+  ia.level_mode = 1;
+  ia.tile = v->tile();
+  rc = launch_init(ws, *v, ia, nseg);
+  if (rc) return rc;
+  const int grid = stage_grid(*v, *di, ws.caps);
+  rc = launch_stage(ws, *v, stage_args(ws, *v, 0, d_pivot, 0, 0), grid);
+  if (rc) return rc;
+  KSORT_HIP(hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, stream));
+  KSORT_HIP(hipStreamSynchronize(stream));
+  if (ws.h_flags->overflow) return fail(KSORT_EINTERNAL, "device consistency check failed");
+  if (ws.h_flags->err) return fail(KSORT_EINVAL, "a segment is outside [0, n) or has len < 1");
+  return KSORT_OK;
+}
+
+}  // namespace ksort
+
+// ============================================================== C ABI
+
+using namespace ksort;
+
+extern "C" {
+
+int ksort_sort_ex(int dtype, void* d_data, int64_t n, int64_t* d_first_pivot, const ksort_tuning* tune,
+                  void* stream) {
+  return run_sort(dtype, d_data, n, nullptr, 1, d_first_pivot, tune, (hipStream_t)stream, false);
+}
+
+int ksort_f64(double* d_data, int64_t n, void* stream) {
+  return run_sort(KSORT_F64, d_data, n, nullptr, 1, nullptr, nullptr, (hipStream_t)stream, false);
+}
+
+int ksort_f32(float* d_data, int64_t n, void* stream) {
+  return run_sort(KSORT_F32, d_data, n, nullptr, 1, nullptr, nullptr, (hipStream_t)stream, false);
+}
+
+int ksort_partition_level(int dtype, const void* d_in, void* d_out, int64_t n, const int64_t* d_seg_left,
+                          const int64_t* d_seg_len, int64_t nseg, int64_t* d_pivot, void* stream) {
+  return run_level(dtype, d_in, d_out, n, d_seg_left, d_seg_len, nseg, d_pivot, (hipStream_t)stream);
+}
+
+int ksort_segmented(int dtype, void* d_packed, int64_t n_total, const int64_t* d_offsets, int64_t nseg,
+                    int64_t* d_first_pivots, const ksort_tuning* tune, void* stream) {
+  if (nseg < 0) return fail(KSORT_EINVAL, "negative nseg");
+  if (nseg > 0 && !d_offsets) return fail(KSORT_EINVAL, "null offsets");
+  if (n_total > 0 && !d_packed) return fail(KSORT_EINVAL, "null data pointer");
+  return run_sort(dtype, d_packed, n_total, d_offsets, nseg, d_first_pivots, tune, (hipStream_t)stream, true);
+}
+
+int ksort_variants(int dtype, ksort_tuning* out, int cap) {
+  if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
+  int cnt = 0;
+  for (const auto& v : variants()) {
+    if (v.dtype != dtype) continue;
+    if (out && cnt < cap) {
+      out[cnt].block = v.block;
+      out[cnt].items = v.items;
+      out[cnt].cutoff = v.cutoff;
+      out[cnt].reserved = 0;
+    }
+    ++cnt;
+  }
+  return cnt;
+}
+
+int ksort_get_default(int dtype, ksort_tuning* out) {
+  const Variant* v = find_variant(dtype, nullptr);
+  if (!v || !out) return fail(KSORT_EINVAL, "bad dtype or null output");
+  out->block = v->block;
+  out->items = v->items;
+  out->cutoff = v->cutoff;
+  out->reserved = 0;
+  return KSORT_OK;
+}
+
+int ksort_set_default(int dtype, const ksort_tuning* tune) { return set_default_variant(dtype, tune); }
+
+int ksort_profile_enable(int on) {
+  g_profile.store(on ? 1 : 0);
+  return KSORT_OK;
+}
+
+int64_t ksort_profile_count(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return (int64_t)g_prof.size();
+}
+
+int64_t ksort_profile_read(ksort_level_record* out, int64_t cap) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  const int64_t n = std::min<int64_t>(cap, (int64_t)g_prof.size());
+  if (out && n > 0) memcpy(out, g_prof.data(), (size_t)n * sizeof(ksort_level_record));
+  g_prof.clear();
+  return n;
+}
+
+size_t ksort_workspace_bytes(int dtype, int64_t n, int64_t nseg) {
+  const Variant* v = find_variant(dtype, nullptr);
+  if (!v || n < 0 || nseg < 0) return 0;
+  const Caps c = caps_for(*v, n, nseg, false);
+  return arena_bytes_for(c, 256) + (size_t)n * v->key_bytes;
+}
+
+int ksort_release_workspaces(void) {
+  {
+    std::lock_guard<std::mutex> gl(g_graph_mu);
+    for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second.exec);
+    g_graphs.clear();
+  }
+  release_workspaces();
+  return KSORT_OK;
+}
+
+const char* ksort_strerror(int code) {
+  switch (code) {
+    case KSORT_OK: return "ok";
+    case KSORT_EINVAL: return "invalid argument";
+    case KSORT_ENOMEM: return "out of memory";
+    case KSORT_EHIP: return "HIP runtime error";
+    case KSORT_EUNSUPPORTED: return "unsupported device (gfx950 required)";
+    case KSORT_ETOOLARGE: return "request exceeds the server budget";
+    case KSORT_EAGAIN: return "server queue full";
+    case KSORT_ECANCELLED: return "cancelled";
+    case KSORT_ETIMEOUT: return "timed out";
+    case KSORT_ENOTFOUND: return "unknown ticket";
+    case KSORT_EINTERNAL: return "internal error";
+    default: return "unknown error";
+  }
+}
+
+const char* ksort_last_error(void) { return t_last_error.c_str(); }
+
+const char* ksort_version(void) { return "ksort-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -110,6 +110,57 @@ def serve_requests(count: int, size_seed: int, dtype_seed: int, arrival_seed: in
 
 REQUEST_SEED_BASE = 1_000_000
 
+
+# ---------------------------------------------------------------- torch twin
+# The same counter-based generator written with torch int64 arithmetic, so
+# large inputs can be drawn directly in device memory.  int64 products wrap
+# modulo 2^64 exactly like the uint64 ones above; right shifts are made
+# logical by masking.  test_synth checks it bit for bit against numpy.
+
+def _to_i64(c: int) -> int:
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+_G64, _M164, _M264 = _to_i64(0x9E3779B97F4A7C15), _to_i64(0xBF58476D1CE4E5B9), _to_i64(0x94D049BB133111EB)
+
+
+def _srl(z, k: int):
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def torch_splitmix64(seed: int, start: int, count: int, device="cpu"):
+    import torch
+    t = torch.arange(start + 1, start + 1 + count, dtype=torch.int64, device=device)
+    z = t * _G64 + _to_i64(seed & 0xFFFFFFFFFFFFFFFF)
+    z = (z ^ _srl(z, 30)) * _M164
+    z = (z ^ _srl(z, 27)) * _M264
+    return z ^ _srl(z, 31)
+
+
+def torch_fill(kind: str, seed: int, n: int, device="cpu", chunk: int = 1 << 26):
+    """Device-resident twin of uniform_f64 / uniform_f32 / grid16_f64."""
+    import torch
+    dt = torch.float32 if kind == "uniform_f32" else torch.float64
+    out = torch.empty(n, dtype=dt, device=device)
+    for s in range(0, n, chunk):
+        c = min(chunk, n - s)
+        z = torch_splitmix64(seed, s, c, device)
+        if kind == "uniform_f64":
+            out[s:s + c] = _srl(z, 11).to(torch.float64) * (2.0 ** -53)
+        elif kind == "uniform_f32":
+            out[s:s + c] = (_srl(z, 40).to(torch.float64) * (2.0 ** -24)).to(torch.float32)
+        elif kind == "grid16_f64":
+            out[s:s + c] = _srl(z, 48).to(torch.float64) * (2.0 ** -16)
+        else:
+            raise ValueError(kind)
+        del z
+    return out
+
+
+def torch_make(name: str, device="cpu"):
+    w = WORKLOADS[name]
+    return torch_fill(w["kind"], w["seed"], w["n"], device)
+
 # Named workloads: (description, seed) in the shapes the benchmark and the
 # parity tests use.
 WORKLOADS = {

@@ -1,0 +1,79 @@
+"""The C-ABI library loads and exports every entry point include/ksort.h
+declares; host-only entry points answer without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ksort.h")
+
+
+def declared_symbols():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"KSORT_API\s+[\w\s\*]+?\b(ksort_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1107_3622_amd import ksort
+    if not os.path.exists(ksort.LIB_PATH):
+        from paper_1107_3622_amd import build
+        build.build()
+    return ksort.load()
+
+
+def test_header_declares_the_planned_surface():
+    syms = declared_symbols()
+    for s in ("ksort_f64", "ksort_f32", "ksort_sort_ex", "ksort_partition_level", "ksort_segmented",
+              "ksort_server_create", "ksort_server_submit", "ksort_server_wait", "ksort_server_destroy",
+              "ksort_strerror", "ksort_last_error", "ksort_autotune"):
+        assert s in syms
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert missing == []
+
+
+def test_binding_covers_every_symbol():
+    from paper_1107_3622_amd import ksort
+    assert sorted(ksort.SIGNATURES) == declared_symbols()
+
+
+def test_host_only_calls(lib):
+    assert lib.ksort_version().decode().startswith("ksort")
+    assert lib.ksort_strerror(0) == b"ok"
+    assert lib.ksort_strerror(-1) == b"invalid argument"
+    from paper_1107_3622_amd import ksort
+    v64 = ksort.ksort_variants(ksort.KSORT_F64)
+    v32 = ksort.ksort_variants(ksort.KSORT_F32)
+    assert (256, 16, 2048) in v64 and (256, 16, 2048) in v32
+    assert ksort.ksort_get_default(ksort.KSORT_F64) == (256, 16, 2048)
+    assert lib.ksort_variants(7, None, 0) == -1
+    # workspace: scratch of n keys plus descriptors, grows with n
+    b1 = ksort.ksort_workspace_bytes(ksort.KSORT_F64, 1_000_000)
+    b2 = ksort.ksort_workspace_bytes(ksort.KSORT_F64, 2_000_000)
+    assert 8_000_000 < b1 < b2
+    assert ksort.ksort_workspace_bytes(5, 10, 1) == 0
+
+
+def test_set_default_rejects_unknown_variant(lib):
+    from paper_1107_3622_amd import ksort
+    with pytest.raises(ksort.KsortError):
+        ksort.ksort_set_default(ksort.KSORT_F64, (256, 3, 2048))
+    ksort.ksort_set_default(ksort.KSORT_F64, (512, 8, 2048))
+    assert ksort.ksort_get_default(ksort.KSORT_F64) == (512, 8, 2048)
+    ksort.ksort_set_default(ksort.KSORT_F64, None)
+    assert ksort.ksort_get_default(ksort.KSORT_F64) == (256, 16, 2048)
+
+
+def test_product_path_has_no_cpu_fallback():
+    # the binding must not import the oracle or any CPU sort
+    pkg = os.path.join(ROOT, "paper_1107_3622_amd")
+    for f in os.listdir(pkg):
+        if f.endswith(".py"):
+            src = open(os.path.join(pkg, f)).read()
+            assert "import oracle" not in src and "from oracle" not in src
+            assert "np.sort" not in src and "torch.sort" not in src

@@ -1,0 +1,117 @@
+"""GPU parity: the HIP sort (through the C ABI) against the literal CPU
+oracle, bit for bit, with the first partition's pivot index."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import assert_bit_equal, note, oracle_sorted, to_dev, to_host, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ks():
+    torch_dev()
+    from paper_1107_3622_amd import ksort
+    ksort.load()
+    return ksort
+
+
+def gpu_sort(ks, a: np.ndarray, tune=None):
+    t = to_dev(a)
+    fp = ks.sort_(t, tune=tune)
+    return to_host(t), fp
+
+
+def check(ks, a, what, tune=None):
+    note(f"{what} n={a.size} dtype={a.dtype} tune={tune}")
+    got, fp = gpu_sort(ks, a, tune)
+    want, wfp = oracle_sorted(a)
+    assert_bit_equal(got, want, what)
+    assert fp == wfp, f"{what}: first pivot {fp} != oracle {wfp}"
+
+
+def test_illustration(ks):
+    a = np.array([55, 66, 60, 78, 22, 50, 75, 5, 8, 94], dtype=np.float64)
+    got, fp = gpu_sort(ks, a)
+    assert list(got) == [5, 8, 22, 50, 55, 60, 66, 75, 78, 94]
+    assert fp == 4
+    got32, fp32 = gpu_sort(ks, a.astype(np.float32))
+    assert list(got32) == [5, 8, 22, 50, 55, 60, 66, 75, 78, 94] and fp32 == 4
+
+
+SIZES = [0, 1, 2, 3, 5, 63, 64, 65, 255, 256, 257, 1000, 2047, 2048, 2049, 2050, 4095, 4096, 4097,
+         6000, 8191, 8192, 8193, 12289, 65537, 100_003, 250_001]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kind", ["uniform_f64", "uniform_f32"])
+def test_sizes_bit_exact(ks, n, kind):
+    a = synth.uniform_f64(500 + n, n) if kind == "uniform_f64" else synth.uniform_f32(500 + n, n)
+    check(ks, a, f"{kind} n={n}")
+
+
+def test_c0_n1e5(ks):
+    check(ks, synth.make("c0_n1e5_f64"), "c0 n=1e5 seed 1")
+
+
+@pytest.mark.parametrize("variant", [(256, 16, 2048), (256, 8, 2048), (512, 8, 2048), (256, 16, 1024)])
+def test_every_variant(ks, variant):
+    for dt in ("f64", "f32"):
+        a = synth.uniform_f64(31, 300_007) if dt == "f64" else synth.uniform_f32(31, 300_007)
+        check(ks, a, f"variant {variant} {dt}", tune=variant)
+
+
+def test_duplicates(ks):
+    check(ks, synth.grid16_f64(8, 300_000), "2^16 grid n=3e5")
+    # four distinct values: long runs of equal keys (one key per level)
+    a = np.floor(synth.uniform_f64(9, 20_000) * 4).astype(np.float64)
+    check(ks, a, "four values n=2e4")
+    check(ks, np.full(9000, 0.25), "all equal n=9000")
+
+
+def test_sorted_and_reversed(ks):
+    a = np.sort(synth.uniform_f64(10, 12_000))
+    check(ks, a, "sorted n=12000")
+    check(ks, a[::-1].copy(), "reversed n=12000")
+
+
+def test_special_values_order(ks):
+    # infinities and subnormals sort like any other keys; no NaN, one zero sign
+    a = synth.uniform_f64(11, 50_000) - 0.5
+    a[::97] = np.inf
+    a[::89] = -np.inf
+    a[::83] = 5e-324
+    a[a == 0] = 0.0
+    a = np.where(a == 0, 0.0, a)
+    check(ks, a, "infinities and subnormals")
+
+
+def test_c1_headline_n7e6(ks):
+    check(ks, synth.make("c1_n7e6_f64"), "c1 n=7e6 seed 4")
+
+
+def test_repeat_is_deterministic(ks):
+    torch = torch_dev()
+    a = synth.uniform_f64(12, 1_000_000)
+    want, wfp = oracle_sorted(a)
+    src = to_dev(a)
+    for r in range(5):
+        note(f"repeat {r}")
+        t = src.clone()
+        fp = ks.sort_(t)
+        assert fp == wfp
+        assert torch.equal(t, to_dev(want))
+
+
+def test_errors(ks):
+    torch = torch_dev()
+    t = torch.zeros(10, dtype=torch.float64, device="cuda")
+    lib = ks.load()
+    assert lib.ksort_f64(None, 10, None) == -1
+    assert lib.ksort_f64(t.data_ptr(), -1, None) == -1
+    assert lib.ksort_sort_ex(3, t.data_ptr(), 10, None, None, None) == -1
+    with pytest.raises(ks.KsortError):
+        ks.ksort_sort_ex(t, tune=(256, 3, 2048))
+    with pytest.raises(TypeError):
+        ks.ksort_f32(t)

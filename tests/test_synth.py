@@ -57,3 +57,16 @@ def test_serve_stream():
     assert sizes.min() >= 1000 and sizes.max() <= 10**7
     assert 0.65 < is64.mean() < 0.75
     assert np.all(np.diff(t) >= 0) and abs(t[-1] / 2000 - 0.01) < 0.002
+
+
+def test_torch_twin_matches_numpy():
+    import torch
+    for seed in (0, 1, 12345, 2**63 + 5):
+        a = synth.splitmix64(seed, 10, 5000).view(np.int64)
+        b = synth.torch_splitmix64(seed, 10, 5000).numpy()
+        assert np.array_equal(a, b)
+    for kind, f in (("uniform_f64", synth.uniform_f64), ("uniform_f32", synth.uniform_f32),
+                    ("grid16_f64", synth.grid16_f64)):
+        x = f(7, 100_003)
+        y = synth.torch_fill(kind, 7, 100_003, chunk=30_000).numpy()
+        assert x.dtype == y.dtype and np.array_equal(x.view(np.uint8), y.view(np.uint8))
