@@ -85,13 +85,22 @@ def main() -> int:
     src = synth.torch_fill(w["kind"], w["seed"], n, dev)
     sort_fn = ksort.ksort_f64 if src.dtype == torch.float64 else ksort.ksort_f32
     key_bytes = src.element_size()
-    copies = [src.clone() for _ in range(args.steps + args.warmup)]
+    copies = [src.clone() for _ in range(2 * args.steps + args.warmup)]
     torch.cuda.synchronize()
 
     for k in range(args.warmup):
         sort_fn(copies[k])
     torch.cuda.synchronize()
     log("warmup done")
+
+    # plain timed region (no per-level events)
+    torch.cuda.synchronize()
+    u0 = time.perf_counter()
+    for k in range(args.steps):
+        sort_fn(copies[args.warmup + args.steps + k])
+    torch.cuda.synchronize()
+    unprofiled = time.perf_counter() - u0
+    log(f"unprofiled: {args.steps} steps in {unprofiled:.4f} s")
 
     # timed region: K whole sorts, each level pass bracketed by HIP events on
     # the library's stream (the current stream)
@@ -118,8 +127,8 @@ def main() -> int:
     passes_per_key = sum(r["live_keys"] for r in recs) / (n * args.steps)
 
     # correctness of the timed output: sorted order equal to the library sort
-    # of torch (an independent check), first pivot from the closed form
-    last = copies[-1]
+    # of torch (an independent check)
+    last = copies[args.warmup + args.steps - 1]
     ref = torch.sort(src.clone())[0]
     ok = bool(torch.equal(last, ref))
 
@@ -147,6 +156,7 @@ def main() -> int:
         "levels_per_sort": stages_per_sort,
         "partition_passes_per_key": passes_per_key,
         "verified_sorted_equal_torch_sort": ok,
+        "ms_per_step_without_level_events": unprofiled / args.steps * 1e3,
     }
     if not args.no_cpu:
         log("timing the CPU oracle")

@@ -74,12 +74,13 @@ struct Workspace {
   int32_t* tilemap[2] = {nullptr, nullptr};
   Seg* fin[2] = {nullptr, nullptr};
   uint64_t* status = nullptr;
-  BufPair* bufs = nullptr;
   int64_t* stage_keys = nullptr;
   int32_t* pending = nullptr;
   int32_t* done_stage = nullptr;
   uint32_t epoch = 0;         // last epoch used
   Flags* h_flags = nullptr;   // pinned readback
+  hipStream_t capture = nullptr;  // private stream used only to record graphs
+  std::vector<hipEvent_t> events; // pool for per-level timing (profiling mode)
   std::mutex mu;
   ~Workspace();
   // make room for a run; scratch_keys * key_bytes bytes of scratch

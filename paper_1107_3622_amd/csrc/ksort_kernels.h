@@ -1,27 +1,28 @@
 // K-sort device kernels for gfx950 (CDNA4, wave64).
 //
 // The paper's method (arXiv 1107.3622, Section 1.1) partitions a[left..right]
-// around key = a[left]: keys that compare `key <= x` false go left of the key,
+// around key = a[left]: keys for which `key <= x` is false go left of the key,
 // the others right, and both sides are then treated the same way.  Step-4
 // leaves the key at i = left + (number of keys smaller than it); Steps 5-6
 // recurse on [left, i-1] and [i+1, right]; a side with one key is final
 // (Section 1.2 note).
 //
-// Here every "level" of that recursion is one data-parallel pass over all
-// live segments at once (the stage kernel):
-//   * partition work: each live segment is cut into tiles of BLOCK*ITEMS
+// Every level of that recursion is one data-parallel pass over all live
+// segments at once (the stage kernel), with two kinds of work:
+//   * partition tiles: each live segment is cut into tiles of BLOCK*ITEMS
 //     keys.  A tile classifies its keys against the segment's key with one
 //     compare each, counts them with wave ballots and popcounts, scans the
 //     per-wave counts in LDS, obtains the count of smaller keys in the
 //     segment's earlier tiles by decoupled look-back, and scatters its keys
-//     through an LDS staging buffer into two contiguous runs of the
-//     ping-pong buffer: smaller keys filling [left, i-1] upward, the others
-//     filling [i+1, right] downward (so no separate counting pass is needed
-//     to know i).  The segment's last tile knows i, writes the key to its
+//     from registers into the ping-pong buffer: smaller keys fill [left, i-1]
+//     upward, the others fill [i+1, right] downward, so i need not be known
+//     in advance.  The segment's last tile knows i, writes the key to its
 //     final place in the caller's array and emits the two sides.
-//   * finish work: a segment of at most CUT keys is loaded into LDS once and
-//     sorted there by the same rule, level after level, then written to its
-//     final place.
+//   * finish tasks: a segment of at most CUT keys is loaded into LDS once
+//     and sorted there by the same rule: the block's waves take sub-segments
+//     from an LDS queue, partition one with wave ballots between two LDS
+//     buffers (more than 64 keys) or finish it in registers (64 keys or
+//     fewer), and write every key straight to its final place.
 // Both kinds of work come from one ticket counter per stage, partition tiles
 // first, so a persistent grid drains the stage without host involvement.
 #pragma once
@@ -38,21 +39,38 @@ constexpr int kWave = 64;
 // ---------------------------------------------------------------------------
 // small helpers
 
+// Pointers into device memory.  Descriptors carry generic pointers; casting
+// them to the global address space, with a wave-uniform base and 32-bit byte
+// offsets, lets the compiler use global loads and stores with a scalar base
+// register instead of flat accesses with 64-bit per-lane addresses.
+#define KS_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ T gld(const void* base, uint32_t byte_off) {
+  return *(const KS_GLOBAL T*)((const KS_GLOBAL char*)base + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void gst(void* base, uint32_t byte_off, T v) {
+  *(KS_GLOBAL T*)((KS_GLOBAL char*)base + byte_off) = v;
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 __device__ __forceinline__ int mbcnt(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
 }
 
-template <typename I>
-__device__ __forceinline__ I uniform(I v) {
-  return (I)__builtin_amdgcn_readfirstlane((int)v);
-}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
   uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p) {
+  return (P*)uniform64((int64_t)(uintptr_t)p);
 }
 
 template <typename I>
@@ -66,6 +84,10 @@ __device__ __forceinline__ void st_agent(I* p, I v) {
 template <typename I>
 __device__ __forceinline__ I add_agent(I* p, I v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename I>
+__device__ __forceinline__ I ld_group(I* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Inclusive prefix sum across the 64 lanes of a wave.
@@ -85,6 +107,18 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
   return v;
 }
 
+// Value x of every lane goes to lane dst (the lanes' dst form a permutation).
+__device__ __forceinline__ int lane_push(int x, int dst) { return __builtin_amdgcn_ds_permute(dst << 2, x); }
+__device__ __forceinline__ float lane_push(float x, int dst) {
+  return __int_as_float(__builtin_amdgcn_ds_permute(dst << 2, __float_as_int(x)));
+}
+__device__ __forceinline__ double lane_push(double x, int dst) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)u);
+  const int hi = __builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
 // Look-back word: count in bits 0..39, flag in 40..41, epoch in 42..63.
 constexpr uint64_t kFlagAgg = 1;   // tile's own count of smaller keys
 constexpr uint64_t kFlagPre = 2;   // count over the segment up to and including the tile
@@ -92,9 +126,81 @@ __device__ __forceinline__ uint64_t status_word(uint32_t epoch, uint64_t flag, u
   return ((uint64_t)epoch << 42) | (flag << 40) | count;
 }
 
-// Finish-list packing of an in-LDS sub-segment: start in the low 16 bits,
-// length in the high 16 bits.
-__device__ __forceinline__ uint32_t pack_sub(uint32_t l, uint32_t len) { return l | (len << 16); }
+// ---------------------------------------------------------------------------
+// work items
+
+constexpr int kTaskNone = 0;
+constexpr int kTaskTile = 1;
+constexpr int kTaskFinish = 2;
+
+struct Task {
+  Seg seg;
+  int32_t kind;
+  int32_t t;  // the ticket
+};
+
+__device__ __forceinline__ void load_seg(Seg* d, const KS_GLOBAL Seg* s) {
+  d->left = s->left;
+  d->len = s->len;
+  d->data = s->data;
+  d->scratch = s->scratch;
+  d->root = s->root;
+  d->buf = s->buf;
+  d->parity = s->parity;
+  d->first_tile = s->first_tile;
+}
+__device__ __forceinline__ void store_seg(KS_GLOBAL Seg* d, const Seg& s) {
+  d->left = s.left;
+  d->len = s.len;
+  d->data = s.data;
+  d->scratch = s.scratch;
+  d->root = s.root;
+  d->buf = s.buf;
+  d->parity = s.parity;
+  d->first_tile = s.first_tile;
+}
+
+// Claims the next ticket of the stage and resolves it to a work item
+// (executed by one thread; the result goes to LDS for the block).
+__device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, int32_t ntiles, int32_t nwork,
+                                           Task* out) {
+  const int par = a.stage & 1;
+  const int32_t t = add_agent(&cur->ticket, 1);
+  out->t = t;
+  if (t < ntiles) {
+    const int32_t slot = ((const KS_GLOBAL int32_t*)a.tilemap[par])[t];
+    load_seg(&out->seg, (const KS_GLOBAL Seg*)a.live[par] + slot);
+    out->kind = kTaskTile;
+  } else if (t < nwork) {
+    load_seg(&out->seg, (const KS_GLOBAL Seg*)a.fin[par] + (t - ntiles));
+    out->kind = kTaskFinish;
+  } else {
+    out->kind = kTaskNone;
+  }
+}
+
+// A work item read from LDS, with every field wave-uniform.
+struct TaskU {
+  int64_t left, len;
+  void* data;
+  void* scratch;
+  int32_t root, buf, parity, first_tile, kind, t;
+};
+
+__device__ __forceinline__ TaskU read_task(const Task* tk) {
+  TaskU u;
+  u.left = uniform64(tk->seg.left);
+  u.len = uniform64(tk->seg.len);
+  u.data = uniform_ptr(tk->seg.data);
+  u.scratch = uniform_ptr(tk->seg.scratch);
+  u.root = uniform(tk->seg.root);
+  u.buf = uniform(tk->seg.buf);
+  u.parity = uniform(tk->seg.parity);
+  u.first_tile = uniform(tk->seg.first_tile);
+  u.kind = uniform(tk->kind);
+  u.t = uniform(tk->t);
+  return u;
+}
 
 // ---------------------------------------------------------------------------
 // shared memory layouts
@@ -102,7 +208,6 @@ __device__ __forceinline__ uint32_t pack_sub(uint32_t l, uint32_t len) { return 
 template <typename T, int BLOCK, int ITEMS>
 struct PartSmem {
   static constexpr int NW = BLOCK / kWave;
-  T stage[BLOCK * ITEMS];
   int32_t off_lt[ITEMS * NW];
   int32_t off_ge[ITEMS * NW];
   int64_t xlt;
@@ -113,11 +218,10 @@ struct PartSmem {
 template <typename T, int BLOCK, int CUT>
 struct FinSmem {
   static constexpr int NW = BLOCK / kWave;
-  static constexpr int FI = CUT / BLOCK;
-  T keys[CUT];
-  uint32_t sub[CUT];
-  uint32_t pre[CUT + 1];
-  int32_t off[FI * NW];
+  static constexpr int QCAP = CUT + NW + 2;
+  T buf[2][CUT];       // ping-pong buffers of the segment
+  uint32_t q[QCAP];    // sub-segment queue; 0 = slot not yet written
+  int32_t q_head, q_tail, outstanding;
 };
 
 template <typename T, int BLOCK, int ITEMS, int CUT>
@@ -127,34 +231,58 @@ union StageSmem {
 };
 
 // ---------------------------------------------------------------------------
-// decoupled look-back: returns the number of smaller keys in tiles
-// first_tile .. t-1 of the segment.  Executed by one whole wave.
+// decoupled look-back: the number of smaller keys in tiles first_tile .. t-1
+// of the segment.  Executed by one whole wave.  Each round examines
+// kLookBack*64 predecessors (lane j, slot r watches tile t-1-j-64r, so slot 0
+// holds the nearest 64), which lets the front of published prefixes advance
+// that many tiles per memory round trip.
+
+constexpr int kLookBack = 4;
 
 __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int32_t first_tile) {
   const int lane = lane_id();
   int64_t excl = 0;
-  int32_t j = t - 1 - lane;
+  int32_t base = t - 1;
   for (;;) {
-    const bool in_seg = j >= first_tile;
-    uint64_t w = 0;
-    uint64_t flag = 0;
-    if (in_seg) {
-      for (;;) {
-        w = ld_agent(a.status + j);
-        flag = (w >> 40) & 3;
-        if ((uint32_t)(w >> 42) == a.epoch && flag != 0) break;
-        __builtin_amdgcn_s_sleep(1);
+    uint64_t w[kLookBack];
+    bool in_seg[kLookBack];
+#pragma unroll
+    for (int r = 0; r < kLookBack; ++r) {
+      const int32_t j = base - lane - kWave * r;
+      in_seg[r] = j >= first_tile;
+      w[r] = in_seg[r] ? ld_agent(a.status + j) : 0;
+    }
+    // wait (per lane) until every watched predecessor has published
+    for (;;) {
+      bool ready = true;
+#pragma unroll
+      for (int r = 0; r < kLookBack; ++r) {
+        const bool ok = (uint32_t)(w[r] >> 42) == a.epoch && ((w[r] >> 40) & 3) != 0;
+        ready = ready && (!in_seg[r] || ok);
+      }
+      if (ready) break;
+      __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+      for (int r = 0; r < kLookBack; ++r) {
+        const int32_t j = base - lane - kWave * r;
+        const bool ok = (uint32_t)(w[r] >> 42) == a.epoch && ((w[r] >> 40) & 3) != 0;
+        if (in_seg[r] && !ok) w[r] = ld_agent(a.status + j);
       }
     }
-    const uint64_t pre_mask = __ballot(in_seg && flag == kFlagPre);
-    int64_t c = in_seg ? (int64_t)(w & ((1ull << 40) - 1)) : 0;
-    if (pre_mask) {
-      const int stop = __builtin_ctzll(pre_mask);  // nearest predecessor with a full prefix
-      if (lane > stop) c = 0;
-      return excl + wave_sum64(c);
+    // nearest predecessor with a full prefix: first slot with one, lowest lane
+#pragma unroll
+    for (int r = 0; r < kLookBack; ++r) {
+      const bool pre = in_seg[r] && ((w[r] >> 40) & 3) == kFlagPre;
+      const uint64_t pre_mask = __ballot(pre);
+      int64_t c = in_seg[r] ? (int64_t)(w[r] & ((1ull << 40) - 1)) : 0;
+      if (pre_mask) {
+        const int stop = __builtin_ctzll(pre_mask);
+        if (lane > stop) c = 0;
+        return excl + wave_sum64(c);
+      }
+      excl += wave_sum64(c);
     }
-    excl += wave_sum64(c);
-    j -= kWave;
+    base -= kWave * kLookBack;
   }
 }
 
@@ -166,14 +294,14 @@ __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int3
 // this stage's input.
 template <typename T, int TILE>
 __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_first, int32_t* em_nt,
-                              int64_t left, int64_t len, int64_t total_lt, T key, int32_t root,
-                              int32_t bufi, int32_t parity, const BufPair& bp) {
+                              const TaskU& tk, int64_t total_lt, T key) {
   const int tid = threadIdx.x;
   const int par = a.stage & 1;
+  const int64_t left = tk.left, len = tk.len;
   const int64_t i = left + total_lt;
   if (tid == 0) {
-    ((T*)bp.data)[i] = key;
-    if (root >= 0 && a.pivot_out) a.pivot_out[root] = a.pivot_relative ? total_lt : i;
+    *((KS_GLOBAL T*)tk.data + i) = key;
+    if (tk.root >= 0 && a.pivot_out) a.pivot_out[tk.root] = a.pivot_relative ? total_lt : i;
     int nchild = 0;
     em_nt[0] = em_nt[1] = 0;
     if (a.emit_children) {
@@ -183,6 +311,15 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
       const int64_t cn[2] = {total_lt, len - 1 - total_lt};
       uint64_t live_keys = 0, fin_keys = 0;
       for (int c = 0; c < 2; ++c) {
+        Seg d;
+        d.left = cl[c];
+        d.len = cn[c];
+        d.data = tk.data;
+        d.scratch = tk.scratch;
+        d.root = -1;
+        d.buf = tk.buf;
+        d.parity = tk.parity ^ 1;
+        d.first_tile = 0;
         if (cn[c] > a.cutoff) {
           const int32_t nt = (int32_t)((cn[c] + TILE - 1) / TILE);
           const int32_t s = add_agent(&nx->nseg, 1);
@@ -191,19 +328,14 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
             st_agent(&a.flags->overflow, 1);
             continue;
           }
-          Seg* d = a.live[npar] + s;
-          d->left = cl[c];
-          d->len = cn[c];
-          d->root = -1;
-          d->buf = bufi;
-          d->parity = parity ^ 1;
-          d->first_tile = f;
+          d.first_tile = f;
+          store_seg((KS_GLOBAL Seg*)a.live[npar] + s, d);
           em_slot[c] = s;
           em_first[c] = f;
           em_nt[c] = nt;
           ++nchild;
           live_keys += (uint64_t)cn[c];
-        } else if (cn[c] == 1 && parity == 1) {
+        } else if (cn[c] == 1 && tk.parity == 1) {
           // a one-key side written into the caller's array is already final
         } else if (cn[c] >= 1) {
           const int32_t f = add_agent(&nx->nfin, 1);
@@ -211,13 +343,7 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
             st_agent(&a.flags->overflow, 1);
             continue;
           }
-          Seg* d = a.fin[npar] + f;
-          d->left = cl[c];
-          d->len = cn[c];
-          d->root = -1;
-          d->buf = bufi;
-          d->parity = parity ^ 1;
-          d->first_tile = 0;
+          store_seg((KS_GLOBAL Seg*)a.fin[npar] + f, d);
           ++nchild;
           fin_keys += (uint64_t)cn[c];
         }
@@ -229,8 +355,8 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
       }
     }
     if (a.pending) {
-      const int32_t old = add_agent(a.pending + bufi, nchild - 1);
-      if (old + nchild - 1 == 0 && a.done_stage) st_agent(a.done_stage + bufi, a.stage);
+      const int32_t old = add_agent(a.pending + tk.buf, nchild - 1);
+      if (old + nchild - 1 == 0 && a.done_stage) st_agent(a.done_stage + tk.buf, a.stage);
     }
   }
   __syncthreads();
@@ -238,7 +364,7 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
   for (int c = 0; c < 2; ++c) {
     const int32_t nt = em_nt[c];
     if (nt > 0) {
-      int32_t* tm = a.tilemap[par ^ 1] + em_first[c];
+      KS_GLOBAL int32_t* tm = (KS_GLOBAL int32_t*)a.tilemap[par ^ 1] + em_first[c];
       const int32_t s = em_slot[c];
       for (int j = tid; j < nt; j += blockDim.x) tm[j] = s;
     }
@@ -248,276 +374,339 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
 // ---------------------------------------------------------------------------
 // partition work: one tile of one live segment
 
-template <typename T, int BLOCK, int ITEMS, int CUT>
-__device__ void partition_tile(const StageArgs& a, int32_t t, PartSmem<T, BLOCK, ITEMS>& sm) {
+template <typename T, int BLOCK, int ITEMS>
+__device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, BLOCK, ITEMS>& sm,
+                               StageCtr* cur, int32_t ntiles, int32_t nwork, Task* next) {
   constexpr int NW = BLOCK / kWave;
   constexpr int TILE = BLOCK * ITEMS;
-  static_assert(ITEMS * NW <= kWave, "per-wave counts must fit one wave scan");
-  const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-  const int par = a.stage & 1;
+  constexpr int NC = ITEMS * NW;                 // per-(item, wave) counts
+  constexpr int PER = (NC + kWave - 1) / kWave;  // counts scanned per lane
+  static_assert(ITEMS <= 32, "per-thread masks are 32 bits");
+  int tid = threadIdx.x;
+  // Opaque to the optimizer: keeps per-item offsets from being hoisted out of
+  // the persistent loop, where they would hold dozens of registers for its
+  // whole duration.
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & (kWave - 1), w = tid / kWave;
 
-  const int32_t slot = uniform(a.tilemap[par][t]);
-  const Seg* sp = a.live[par] + slot;
-  const int64_t left = uniform64(sp->left);
-  const int64_t len = uniform64(sp->len);
-  const int32_t root = uniform(sp->root);
-  const int32_t bufi = uniform(sp->buf);
-  const int32_t parity = uniform(sp->parity);
-  const int32_t first_tile = uniform(sp->first_tile);
-  const int32_t tidx = t - first_tile;
+  const int32_t tidx = tk.t - tk.first_tile;
+  const int64_t left = tk.left, len = tk.len;
   const int64_t o = (int64_t)tidx * TILE;
   const int32_t cnt = (int32_t)min((int64_t)TILE, len - o);
-  const BufPair bp = a.bufs[bufi];
-  const T* in = (const T*)(parity ? bp.scratch : bp.data);
-  T* out = (T*)(parity ? bp.data : bp.scratch);
-  const T key = in[left];
+  const T* in = (const T*)(tk.parity ? tk.scratch : tk.data);
+  T* out = (T*)(tk.parity ? tk.data : tk.scratch);
+  const T key = gld<T>(in + left, 0);
   const T* src = in + left + o;
 
   // a1/a2: load the tile (striped: item k of thread tid is element k*BLOCK+tid)
-  // and classify against the key.
+  // and classify each key against the segment's key.
+  // Item k of every lane lies below the uniform base src + k*BLOCK; the lane
+  // offset tid*sizeof(T) is shared by all items, and "element exists" is
+  // tid < cnt - k*BLOCK (a uniform bound), so no per-item index registers.
+  const uint32_t toff = (uint32_t)tid * (uint32_t)sizeof(T);
   T v[ITEMS];
+  if (cnt == TILE) {
 #pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    const int e = k * BLOCK + tid;
-    v[k] = (e < cnt) ? src[e] : T(0);
+    for (int k = 0; k < ITEMS; ++k) v[k] = gld<T>(src + k * BLOCK, toff);
+  } else {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) v[k] = (tid < cnt - k * BLOCK) ? gld<T>(src + k * BLOCK, toff) : T(0);
   }
-  int rk[ITEMS];
-  uint32_t is_lt = 0, is_valid = 0;
+  // Per-item counts of the wave are gathered in one register (lane k: smaller
+  // keys of item k, lane ITEMS+k: the others) and written with one store.
+  // (The classification is recomputed, not stored, at scatter time: one
+  // compare is cheaper than the registers a stored mask costs.)
+  const bool not_key = !(tidx == 0 && tid == 0);  // element 0 of tile 0 is the key itself
+  int wcnt = 0;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
-    const int e = k * BLOCK + tid;
-    const bool valid = e < cnt && !(tidx == 0 && e == 0);
+    const bool valid = tid < cnt - k * BLOCK && (k > 0 || not_key);
     const bool lt = valid && !(key <= v[k]);
     const bool ge = valid && !lt;
     const uint64_t bl = __ballot(lt);
     const uint64_t bg = __ballot(ge);
-    rk[k] = lt ? mbcnt(bl) : mbcnt(bg);
-    is_lt |= (uint32_t)lt << k;
-    is_valid |= (uint32_t)valid << k;
-    if (lane == 0) {
-      sm.off_lt[k * NW + w] = __popcll(bl);
-      sm.off_ge[k * NW + w] = __popcll(bg);
-    }
+    wcnt = lane == k ? __popcll(bl) : wcnt;
+    wcnt = lane == ITEMS + k ? __popcll(bg) : wcnt;
   }
+  if (lane < ITEMS)
+    sm.off_lt[lane * NW + w] = wcnt;
+  else if (lane < 2 * ITEMS)
+    sm.off_ge[(lane - ITEMS) * NW + w] = wcnt;
   __syncthreads();
 
-  // a3 (local part): exclusive scan of the per-(item, wave) counts, in element
-  // order; publish this tile's count for the look-back.
+  // a3: exclusive scan of the per-(item, wave) counts in element order, then
+  // the look-back for the smaller keys in the segment's earlier tiles.
   if (w == 0) {
-    const int n = ITEMS * NW;
-    const int cl = lane < n ? sm.off_lt[lane] : 0;
-    const int cg = lane < n ? sm.off_ge[lane] : 0;
-    const int il = wave_inclusive_scan(cl);
-    const int ig = wave_inclusive_scan(cg);
-    if (lane < n) {
-      sm.off_lt[lane] = il - cl;
-      sm.off_ge[lane] = ig - cg;
+    int cl[PER], cg[PER];
+    int sl = 0, sg = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = lane * PER + j;
+      cl[j] = idx < NC ? sm.off_lt[idx] : 0;
+      cg[j] = idx < NC ? sm.off_ge[idx] : 0;
+      sl += cl[j];
+      sg += cg[j];
+    }
+    const int il = wave_inclusive_scan(sl);
+    const int ig = wave_inclusive_scan(sg);
+    int el = il - sl, eg = ig - sg;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = lane * PER + j;
+      if (idx < NC) {
+        sm.off_lt[idx] = el;
+        sm.off_ge[idx] = eg;
+      }
+      el += cl[j];
+      eg += cg[j];
     }
     const int tot_lt = __shfl(il, kWave - 1, kWave);
     const int tot_ge = __shfl(ig, kWave - 1, kWave);
-    if (lane == 0) {
-      sm.tot_lt = tot_lt;
-      sm.tot_ge = tot_ge;
-      st_agent(a.status + t, status_word(a.epoch, tidx == 0 ? kFlagPre : kFlagAgg, (uint64_t)tot_lt));
-    }
-  }
-  __syncthreads();
-
-  // a4 (local part): stage the tile in LDS as [smaller keys | larger-or-equal
-  // keys in reverse rank order], so that each side leaves as one contiguous run.
-  const int tot_lt = sm.tot_lt, tot_ge = sm.tot_ge;
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    if (is_valid & (1u << k)) {
-      const bool lt = is_lt & (1u << k);
-      const int r = (lt ? sm.off_lt[k * NW + w] : sm.off_ge[k * NW + w]) + rk[k];
-      sm.stage[lt ? r : tot_lt + (tot_ge - 1 - r)] = v[k];
-    }
-  }
-  // a3 (global part): smaller keys in the segment's earlier tiles.
-  if (w == 0) {
+    if (lane == 0)
+      st_agent(a.status + tk.t, status_word(a.epoch, tidx == 0 ? kFlagPre : kFlagAgg, (uint64_t)tot_lt));
     int64_t xlt = 0;
     if (tidx > 0) {
-      xlt = look_back(a, t, first_tile);
-      if (lane == 0) st_agent(a.status + t, status_word(a.epoch, kFlagPre, (uint64_t)(xlt + tot_lt)));
+      xlt = look_back(a, tk.t, tk.first_tile);
+      if (lane == 0) st_agent(a.status + tk.t, status_word(a.epoch, kFlagPre, (uint64_t)(xlt + tot_lt)));
     }
-    if (lane == 0) sm.xlt = xlt;
+    if (lane == 0) {
+      sm.xlt = xlt;
+      sm.tot_lt = tot_lt;
+      sm.tot_ge = tot_ge;
+    }
   }
   __syncthreads();
+  // this tile no longer holds anyone up: claim and resolve the next ticket,
+  // hidden behind the scatter below
+  if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
 
-  // a4: write both runs.  Smaller keys fill [left, i-1] upward, the others
-  // fill [i+1, right] downward.  The runs always lie inside the segment; the
-  // check below only guards the device against a corrupted count.
-  const int64_t xlt = sm.xlt;
+  // a4: scatter from registers.  Smaller keys fill [left, i-1] upward, the
+  // others fill [i+1, right] downward.  The runs always lie inside the
+  // segment; the check only guards the device against a corrupted count.
+  const int64_t xlt = uniform64(sm.xlt);
+  const int tot_lt = uniform(sm.tot_lt), tot_ge = uniform(sm.tot_ge);
   const int64_t xge = o - (tidx > 0 ? 1 : 0) - xlt;
   const int64_t right = left + len - 1;
   if (xlt < 0 || xge < 0 || xlt + tot_lt > len - 1 || xge + tot_ge > len - 1) {
     if (tid == 0) st_agent(&a.flags->overflow, 2);
     return;
   }
-  T* dlt = out + left + xlt;
-  T* dge = out + (right - xge - tot_ge + 1);
-  for (int s = tid; s < tot_lt + tot_ge; s += BLOCK) {
-    const T x = sm.stage[s];
-    if (s < tot_lt)
-      dlt[s] = x;
-    else
-      dge[s - tot_lt] = x;
+  T* dlt = out + left + xlt;                  // first slot of this tile's smaller keys
+  T* dge = out + (right - xge - tot_ge + 1);  // lowest slot of its other keys
+  // Opaque copies: the compares below are recomputed rather than kept alive
+  // since the counting loop (a compare costs less than the registers).
+  T key2 = key;
+  int tid2 = tid;
+  asm volatile("" : "+v"(key2), "+v"(tid2));
+  // this wave's offsets, one per lane as when they were counted
+  const int woff = lane < ITEMS ? sm.off_lt[lane * NW + w] : lane < 2 * ITEMS ? sm.off_ge[(lane - ITEMS) * NW + w] : 0;
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const bool valid = tid2 < cnt - k * BLOCK && (k > 0 || tidx != 0 || tid2 != 0);
+    const bool lt = valid && !(key2 <= v[k]);
+    const bool ge = valid && !lt;
+    const int rl = mbcnt(__ballot(lt));
+    const int rg = mbcnt(__ballot(ge));
+    const int ol = __builtin_amdgcn_readlane(woff, k);
+    const int og = __builtin_amdgcn_readlane(woff, ITEMS + k);
+    if (lt) gst<T>(dlt, (uint32_t)((ol + rl) * sizeof(T)), v[k]);
+    if (ge) gst<T>(dge, (uint32_t)((tot_ge - 1 - og - rg) * sizeof(T)), v[k]);
   }
 
   // a5/a6: the segment's last tile places the key and emits the two sides.
-  if (o + cnt == len) {
-    const int64_t total_lt = xlt + tot_lt;
-    emit_children<T, TILE>(a, sm.em_slot, sm.em_first, sm.em_nt, left, len, total_lt, key, root, bufi,
-                           parity, bp);
-  }
+  if (o + cnt == len) emit_children<T, TILE>(a, sm.em_slot, sm.em_first, sm.em_nt, tk, xlt + tot_lt, key);
 }
 
 // ---------------------------------------------------------------------------
-// finish work: a segment of 1..CUT keys sorted in LDS by the same rule
-// (first key of each sub-segment is its key; smaller keys left, the others
-// right), one level per iteration, then written to the caller's array.
+// finish work
+
+constexpr int kSmall = kWave;  // sub-segments of at most this many keys finish in registers
+
+// K-sort of in[0 .. L-1] (1 <= L <= 64) by one wave, in registers, one key
+// per lane; lane j holds position j and (sl, sL) is the sub-segment of that
+// position.  The sorted keys are written to out[0 .. L-1].
+template <typename T, typename In>
+__device__ void wave_ksort(const In* in, T* out, int L, int64_t* pivot_slot, int64_t pivot_bias) {
+  const int lane = lane_id();
+  T v = lane < L ? (T)in[lane] : T(0);
+  int sl = 0, sL = lane < L ? L : 0;
+  bool first = pivot_slot != nullptr;
+  for (;;) {
+    const bool act = sL >= 2;
+    if (__ballot(act) == 0) break;
+    const T key = __shfl(v, sl, kWave);
+    const bool lt = act && lane != sl && !(key <= v);
+    const uint64_t m = __ballot(lt);
+    const int pre = mbcnt(m);
+    const int base_pre = __shfl(pre, sl, kWave);
+    const uint64_t range = (sL >= 64 ? ~0ull : ((1ull << sL) - 1)) << sl;
+    const int tot = __popcll(m & range);  // smaller keys in the sub-segment
+    int dest = lane, nl = sl, nL = sL;
+    if (act) {
+      if (lane == sl) {
+        dest = sl + tot;
+        nl = dest;
+        nL = 1;
+        if (first) *pivot_slot = pivot_bias + tot;
+      } else if (lt) {
+        dest = sl + (pre - base_pre);
+        nL = tot;
+      } else {
+        dest = sl + tot + 1 + (lane - sl - 1 - (pre - base_pre));
+        nl = sl + tot + 1;
+        nL = sL - tot - 1;
+      }
+    }
+    first = false;
+    v = lane_push(v, dest);
+    sl = lane_push(nl, dest);
+    sL = lane_push(nL, dest);
+  }
+  if (lane < L) gst<T>(out, (uint32_t)(lane * sizeof(T)), v);
+}
+
+// One partition of in[s .. s+L-1] into out[s .. s+L-1] by one wave (Steps
+// 1-4 on a sub-segment): smaller keys fill upward from s, the others downward
+// from s+L-1.  Returns the number of smaller keys.  Four 64-key chunks are
+// read before any is written, so one LDS round trip serves four chunks.
+template <typename T>
+__device__ int wave_partition(const T* in, T* out, int s, int L, T key) {
+  constexpr int U = 4;
+  const int lane = lane_id();
+  int cl = 0, cg = 0;
+  const int end = s + L;
+  for (int base = s + 1; base < end; base += U * kWave) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = base + u * kWave + lane;
+      v[u] = x < end ? in[x] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = base + u * kWave + lane;
+      const bool valid = x < end;
+      const bool lt = valid && !(key <= v[u]);
+      const bool ge = valid && !lt;
+      const uint64_t bl = __ballot(lt);
+      const uint64_t bg = __ballot(ge);
+      if (lt) out[s + cl + mbcnt(bl)] = v[u];
+      if (ge) out[end - 1 - cg - mbcnt(bg)] = v[u];
+      cl += __popcll(bl);
+      cg += __popcll(bg);
+    }
+  }
+  return cl;
+}
+
+__device__ __forceinline__ uint32_t q_entry(int s, int L, int p) {
+  return 1u | ((uint32_t)p << 1) | ((uint32_t)s << 2) | ((uint32_t)L << 14);
+}
 
 template <typename T, int BLOCK, int CUT>
-__device__ void finish_segment(const StageArgs& a, int32_t f, FinSmem<T, BLOCK, CUT>& sm) {
+__device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, BLOCK, CUT>& sm, StageCtr* cur,
+                               int32_t ntiles, int32_t nwork, Task* next) {
   constexpr int NW = BLOCK / kWave;
-  constexpr int FI = CUT / BLOCK;
-  static_assert(CUT % BLOCK == 0, "cutoff must be a multiple of the block size");
-  static_assert(FI * NW <= kWave, "per-wave counts must fit one wave scan");
-  const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-  const int par = a.stage & 1;
-
-  const Seg* sp = a.fin[par] + f;
-  const int64_t left = uniform64(sp->left);
-  const int32_t len = uniform((int32_t)sp->len);
-  const int32_t root = uniform(sp->root);
-  const int32_t bufi = uniform(sp->buf);
-  const int32_t parity = uniform(sp->parity);
-  const BufPair bp = a.bufs[bufi];
-  const T* src = (const T*)(parity ? bp.scratch : bp.data) + left;
-  T* dst = (T*)bp.data + left;
-  const int rows = (len + BLOCK - 1) / BLOCK;
+  static_assert(CUT <= 4095, "queue entries hold 12-bit positions and lengths");
+  const int tid = threadIdx.x, lane = lane_id();
+  const int64_t left = tk.left;
+  const int32_t len = (int32_t)tk.len;
+  const T* src = (const T*)(tk.parity ? tk.scratch : tk.data) + left;
+  T* dst = (T*)tk.data + left;
+  const bool want_pivot = tk.root >= 0 && a.pivot_out != nullptr;
+  int64_t* pivot_slot = want_pivot ? a.pivot_out + tk.root : nullptr;
+  const int64_t pivot_bias = a.pivot_relative ? 0 : left;
   if (len < 1 || len > CUT) {  // never produced by the emitters; guards the LDS arrays
     if (tid == 0) st_agent(&a.flags->overflow, 3);
+    if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
     return;
   }
 
-  if (len == 1) {
-    if (tid == 0) {
-      if (parity) dst[0] = src[0];
-      if (root >= 0 && a.pivot_out) a.pivot_out[root] = a.pivot_relative ? 0 : left;
-    }
+  if (len <= kSmall) {
+    // one wave finishes the whole segment in registers (a single key is its
+    // own first pivot)
+    if (tid < kWave) wave_ksort<T>((const KS_GLOBAL T*)src, dst, len, pivot_slot, pivot_bias);
+    if (tid == 0 && len == 1 && pivot_slot) *pivot_slot = pivot_bias;
+    if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
   } else {
-    for (int k = 0; k < FI; ++k) {
-      const int x = k * BLOCK + tid;
-      if (x < len) {
-        sm.keys[x] = src[x];
-        sm.sub[x] = pack_sub(0, (uint32_t)len);
-      }
+    {
+      // all loads in flight before the first LDS store
+      constexpr int FI = CUT / BLOCK;
+      T v[FI];
+#pragma unroll
+      for (int k = 0; k < FI; ++k) v[k] = (tid < len - k * BLOCK) ? gld<T>(src + k * BLOCK, (uint32_t)(tid * sizeof(T))) : T(0);
+#pragma unroll
+      for (int k = 0; k < FI; ++k)
+        if (tid < len - k * BLOCK) sm.buf[0][k * BLOCK + tid] = v[k];
+    }
+    for (int x = tid; x < len + NW + 2; x += BLOCK) sm.q[x] = 0;
+    __syncthreads();
+    if (tid == 0) {
+      sm.q[0] = q_entry(0, len, 0);
+      sm.q_tail = 1;
+      sm.q_head = 0;
+      sm.outstanding = 1;
     }
     __syncthreads();
-    bool first = true;
-    // every level finishes at least one key of each active sub-segment, so
-    // len - 1 levels always suffice; the cap only guards against a hang
-    for (int level = 0;; ++level) {
-      if (level >= len) {
-        if (tid == 0) st_agent(&a.flags->overflow, 4);
-        break;
+    if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
+    // Each wave takes sub-segments from the queue until none is outstanding.
+    // Every branch of this loop is taken on a wave-uniform value (read with
+    // readfirstlane before the test): the lanes must stay together for the
+    // cross-lane operations inside, and a branch on a per-lane load would
+    // let the compiler split them (it may route lanes through different loop
+    // exits when it cannot prove a condition uniform).
+    for (;;) {
+      int idx = 0;
+      if (lane == 0) idx = atomicAdd(&sm.q_head, 1);
+      idx = uniform(idx);
+      uint32_t e = 0;
+      for (;;) {
+        e = (uint32_t)uniform(
+            (int)__hip_atomic_load(&sm.q[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (e != 0) break;
+        if (uniform(ld_group(&sm.outstanding)) == 0) break;
+        __builtin_amdgcn_s_sleep(1);
       }
-      T val[FI];
-      uint32_t sub[FI];
-      int pre[FI];
-      uint32_t flg = 0;
-#pragma unroll
-      for (int k = 0; k < FI; ++k) {
-        if (k >= rows) break;
-        const int x = k * BLOCK + tid;
-        bool fl = false;
-        if (x < len) {
-          sub[k] = sm.sub[x];
-          const uint32_t l = sub[k] & 0xffff, L = sub[k] >> 16;
-          val[k] = sm.keys[x];
-          if (L >= 2 && (uint32_t)x != l) {
-            const T key = sm.keys[l];
-            fl = !(key <= val[k]);
-          }
+      if (e == 0) break;  // everything is done
+      const int p = (e >> 1) & 1, s = (e >> 2) & 0xfff, L = (int)(e >> 14);
+      int pushed = 0;
+      if (L <= kSmall) {
+        wave_ksort<T>(sm.buf[p] + s, dst + s, L, nullptr, 0);
+      } else {
+        const T key = sm.buf[p][s];
+        const int cl = wave_partition<T>(sm.buf[p], sm.buf[p ^ 1], s, L, key);
+        const int cg = L - 1 - cl;
+        if (lane == 0) {
+          gst<T>(dst, (uint32_t)((s + cl) * sizeof(T)), key);  // Step-4: the key is final
+          if (pivot_slot && L == len) *pivot_slot = pivot_bias + cl;
         }
-        const uint64_t m = __ballot(fl);
-        pre[k] = mbcnt(m);
-        flg |= (uint32_t)fl << k;
-        if (lane == 0) sm.off[k * NW + w] = __popcll(m);
-      }
-      __syncthreads();
-      if (w == 0) {
-        const int n = rows * NW;
-        const int c = lane < n ? sm.off[lane] : 0;
-        const int inc = wave_inclusive_scan(c);
-        if (lane < n) sm.off[lane] = inc - c;
-        if (lane == kWave - 1) sm.pre[len] = (uint32_t)inc;
-      }
-      __syncthreads();
+        // Steps 5-6 on the two sides (a side of one key is final)
+        const int cs[2] = {s, s + cl + 1};
+        const int cn[2] = {cl, cg};
 #pragma unroll
-      for (int k = 0; k < FI; ++k) {
-        if (k >= rows) break;
-        const int x = k * BLOCK + tid;
-        pre[k] += sm.off[k * NW + w];
-        if (x < len) sm.pre[x] = (uint32_t)pre[k];
-      }
-      __syncthreads();
-      int dest[FI];
-      uint32_t nsub[FI];
-      int more = 0;
-#pragma unroll
-      for (int k = 0; k < FI; ++k) {
-        if (k >= rows) break;
-        const int x = k * BLOCK + tid;
-        if (x < len) {
-          const uint32_t l = sub[k] & 0xffff, L = sub[k] >> 16;
-          dest[k] = x;
-          nsub[k] = sub[k];
-          if (L >= 2) {
-            const int base = (int)sm.pre[l];
-            const int tot = (int)sm.pre[l + L] - base;  // smaller keys in the sub-segment
-            if ((uint32_t)x == l) {
-              dest[k] = (int)l + tot;
-              nsub[k] = pack_sub((uint32_t)dest[k], 1);
-              if (first && root >= 0 && a.pivot_out)
-                a.pivot_out[root] = a.pivot_relative ? tot : left + tot;
-            } else if (flg & (1u << k)) {
-              dest[k] = (int)l + (pre[k] - base);
-              nsub[k] = pack_sub(l, (uint32_t)tot);
-            } else {
-              const int rge = (x - (int)l - 1) - (pre[k] - base);
-              dest[k] = (int)l + tot + 1 + rge;
-              nsub[k] = pack_sub(l + (uint32_t)tot + 1, L - (uint32_t)tot - 1);
+        for (int c = 0; c < 2; ++c) {
+          if (cn[c] == 1) {
+            if (lane == 0) gst<T>(dst, (uint32_t)(cs[c] * sizeof(T)), sm.buf[p ^ 1][cs[c]]);
+          } else if (cn[c] >= 2) {
+            if (lane == 0) {
+              const int qi = atomicAdd(&sm.q_tail, 1);
+              // release: the side's keys, written above, are seen by the wave that takes it
+              __hip_atomic_store(&sm.q[qi], q_entry(cs[c], cn[c], p ^ 1), __ATOMIC_RELEASE,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            more |= (nsub[k] >> 16) >= 2;
+            ++pushed;
           }
         }
       }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < FI; ++k) {
-        if (k >= rows) break;
-        const int x = k * BLOCK + tid;
-        if (x < len) {
-          sm.keys[dest[k]] = val[k];
-          sm.sub[dest[k]] = nsub[k];
-        }
-      }
-      first = false;
-      if (!__syncthreads_or(more)) break;
+      // the writes of this wave's new entries come before this update
+      if (lane == 0)
+        __hip_atomic_fetch_add(&sm.outstanding, pushed - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    for (int k = 0; k < FI; ++k) {
-      const int x = k * BLOCK + tid;
-      if (x < len) dst[x] = sm.keys[x];
-    }
+    __syncthreads();
   }
-  if (tid == 0) {
-    if (a.pending) {
-      const int32_t old = add_agent(a.pending + bufi, -1);
-      if (old - 1 == 0 && a.done_stage) st_agent(a.done_stage + bufi, a.stage);
-    }
+  if (tid == 0 && a.pending) {
+    const int32_t old = add_agent(a.pending + tk.buf, -1);
+    if (old - 1 == 0 && a.done_stage) st_agent(a.done_stage + tk.buf, a.stage);
   }
 }
 
@@ -527,38 +716,46 @@ __device__ void finish_segment(const StageArgs& a, int32_t f, FinSmem<T, BLOCK, 
 template <typename T, int BLOCK, int ITEMS, int CUT>
 __global__ __launch_bounds__(BLOCK) void stage_kernel(StageArgs a) {
   __shared__ StageSmem<T, BLOCK, ITEMS, CUT> sm;
-  __shared__ int32_t s_ticket;
+  __shared__ Task next;
+  __shared__ int32_t s_counts[2];
   StageCtr* cur = a.ctr + (a.stage % 3);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    StageCtr* nn = a.ctr + ((a.stage + 2) % 3);
-    st_agent(&nn->nseg, 0);
-    st_agent(&nn->ntiles, 0);
-    st_agent(&nn->nfin, 0);
-    st_agent(&nn->ticket, 0);
-  }
-  // after a capacity overflow the lists are incomplete: do nothing (the host
-  // reports the error)
-  if (ld_agent(&a.flags->overflow) != 0) return;
-  const int32_t ntiles = uniform(min(ld_agent(&cur->ntiles), a.cap_tiles));
-  const int32_t nfin = uniform(min(ld_agent(&cur->nfin), a.cap_fin));
-  const int32_t nwork = ntiles + nfin;
-  for (;;) {
-    if (threadIdx.x == 0) s_ticket = add_agent(&cur->ticket, 1);
-    __syncthreads();
-    const int32_t t = uniform(s_ticket);
-    if (t >= nwork) break;
-    if (t < ntiles)
-      partition_tile<T, BLOCK, ITEMS, CUT>(a, t, sm.p);
+  if (threadIdx.x == BLOCK - 1) {
+    if (blockIdx.x == 0) {
+      StageCtr* nn = a.ctr + ((a.stage + 2) % 3);
+      st_agent(&nn->nseg, 0);
+      st_agent(&nn->ntiles, 0);
+      st_agent(&nn->nfin, 0);
+      st_agent(&nn->ticket, 0);
+    }
+    // after a failed consistency check the lists may be incomplete: do
+    // nothing (the host reports the error)
+    const int32_t ovf = ld_agent(&a.flags->overflow);
+    const int32_t nt = min(ld_agent(&cur->ntiles), a.cap_tiles);
+    const int32_t nf = min(ld_agent(&cur->nfin), a.cap_fin);
+    if (ovf != 0)
+      next.kind = kTaskNone;
     else
-      finish_segment<T, BLOCK, CUT>(a, t - ntiles, sm.f);
+      fetch_task(a, cur, nt, nt + nf, &next);
+    s_counts[0] = nt;
+    s_counts[1] = nt + nf;
+  }
+  __syncthreads();
+  const int32_t ntiles = uniform(s_counts[0]);
+  const int32_t nwork = uniform(s_counts[1]);
+  for (;;) {
+    const TaskU tk = read_task(&next);
+    __syncthreads();  // everyone has read `next` before it is overwritten
+    if (tk.kind == kTaskNone) break;
+    if (tk.kind == kTaskTile)
+      partition_tile<T, BLOCK, ITEMS>(a, tk, sm.p, cur, ntiles, nwork, &next);
+    else
+      finish_segment<T, BLOCK, CUT>(a, tk, sm.f, cur, ntiles, nwork, &next);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
 // set-up kernels
-
-
 
 // Zero-fills n 64-bit words (look-back words before a run).
 __global__ void clear_kernel(uint64_t* p, int64_t n) {
@@ -585,16 +782,13 @@ __global__ void reset_kernel(StageCtr* ctr, Flags* flags, int64_t* stage_keys, i
 }
 
 // One block per input array (or per segment in single-level mode): validate,
-// classify into the stage-0 live or finish list, and write the tile map.
+// classify into the lists of stage a.stage (0 for a fresh run; the server
+// admits requests into its current stage) and write the tile map.
 __global__ void init_kernel(InitArgs ia) {
   __shared__ int32_t s_slot, s_first, s_nt;
   const StageArgs& a = ia.sa;
   const int64_t u = blockIdx.x;
   const int tid = threadIdx.x;
-  if (u == 0 && tid == 0) {
-    BufPair* bp = (BufPair*)a.bufs + ia.buf;
-    *bp = ia.pair;
-  }
   int64_t left, len;
   if (ia.offsets) {
     left = ia.offsets[u];
@@ -611,8 +805,6 @@ __global__ void init_kernel(InitArgs ia) {
     if (tid == 0) st_agent(&a.flags->err, 1);
     return;
   }
-  // the arrays join the lists of stage a.stage (0 for a fresh run; the
-  // server admits requests into its current stage)
   const int par = a.stage & 1;
   StageCtr* c0 = a.ctr + (a.stage % 3);
   const int32_t root = ia.root_base + (int32_t)u;
@@ -623,18 +815,21 @@ __global__ void init_kernel(InitArgs ia) {
       st_agent(a.pending + ia.buf, 0);
       if (a.done_stage) st_agent(a.done_stage + ia.buf, -1);
     }
+    Seg d;
+    d.left = left;
+    d.len = len;
+    d.data = ia.pair.data;
+    d.scratch = ia.pair.scratch;
+    d.root = root;
+    d.buf = ia.buf;
+    d.parity = ia.level_mode ? 1 : 0;
+    d.first_tile = 0;
     if (len == 0) {
       if (a.pivot_out) a.pivot_out[root] = -1;
     } else if (!ia.level_mode && len <= a.cutoff) {
       const int32_t f = add_agent(&c0->nfin, 1);
       if (f < a.cap_fin) {
-        Seg* d = a.fin[par] + f;
-        d->left = left;
-        d->len = len;
-        d->root = root;
-        d->buf = ia.buf;
-        d->parity = 0;
-        d->first_tile = 0;
+        a.fin[par][f] = d;
         ++nseg;
         if (a.stage_keys && a.stage < a.cap_stats)
           atomicAdd((unsigned long long*)&a.stage_keys[2 * a.stage + 1], (unsigned long long)len);
@@ -646,13 +841,8 @@ __global__ void init_kernel(InitArgs ia) {
       const int32_t s = add_agent(&c0->nseg, 1);
       const int32_t f = add_agent(&c0->ntiles, nt);
       if (s < a.cap_live && f + nt <= a.cap_tiles) {
-        Seg* d = a.live[par] + s;
-        d->left = left;
-        d->len = len;
-        d->root = root;
-        d->buf = ia.buf;
-        d->parity = ia.level_mode ? 1 : 0;
-        d->first_tile = f;
+        d.first_tile = f;
+        a.live[par][s] = d;
         s_slot = s;
         s_first = f;
         s_nt = nt;

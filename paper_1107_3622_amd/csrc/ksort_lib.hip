@@ -61,14 +61,14 @@ static Variant make_variant(int dtype) {
 
 const std::vector<Variant>& variants() {
   static const std::vector<Variant> vs = {
+      make_variant<double, 256, 32, 2048>(KSORT_F64),
       make_variant<double, 256, 16, 2048>(KSORT_F64),
-      make_variant<double, 256, 8, 2048>(KSORT_F64),
-      make_variant<double, 512, 8, 2048>(KSORT_F64),
-      make_variant<double, 256, 16, 1024>(KSORT_F64),
+      make_variant<double, 512, 16, 2048>(KSORT_F64),
+      make_variant<double, 256, 32, 1024>(KSORT_F64),
+      make_variant<float, 256, 32, 2048>(KSORT_F32),
       make_variant<float, 256, 16, 2048>(KSORT_F32),
-      make_variant<float, 256, 8, 2048>(KSORT_F32),
-      make_variant<float, 512, 8, 2048>(KSORT_F32),
-      make_variant<float, 256, 16, 1024>(KSORT_F32),
+      make_variant<float, 512, 16, 2048>(KSORT_F32),
+      make_variant<float, 256, 32, 1024>(KSORT_F32),
   };
   return vs;
 }
@@ -98,7 +98,7 @@ const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n) {
   }
   std::lock_guard<std::mutex> lk(g_default_mu);
   int j = g_default[dtype];
-  if (j < 0) j = variant_index(dtype, 256, 16, 2048);
+  if (j < 0) j = variant_index(dtype, 256, 32, 2048);
   return &vs[j];
 }
 
@@ -172,13 +172,14 @@ static size_t arena_bytes_for(const Caps& c, int cap_stats) {
   b += 2 * align256((size_t)c.tiles * sizeof(int32_t));
   b += 2 * align256((size_t)c.fin * sizeof(Seg));
   b += align256((size_t)c.tiles * sizeof(uint64_t));
-  b += align256((size_t)c.bufs * sizeof(BufPair));
   b += align256((size_t)cap_stats * 2 * sizeof(int64_t));
   b += 2 * align256((size_t)c.bufs * sizeof(int32_t));
   return b;
 }
 
 Workspace::~Workspace() {
+  for (auto e : events) (void)hipEventDestroy(e);
+  if (capture) (void)hipStreamDestroy(capture);
   if (arena) (void)hipFree(arena);
   if (scratch) (void)hipFree(scratch);
   if (h_flags) (void)hipHostFree(h_flags);
@@ -214,7 +215,6 @@ int Workspace::reserve(const Caps& c, size_t scratch_need) {
     for (int k = 0; k < 2; ++k) tilemap[k] = (int32_t*)take((size_t)nc.tiles * sizeof(int32_t));
     for (int k = 0; k < 2; ++k) fin[k] = (Seg*)take((size_t)nc.fin * sizeof(Seg));
     status = (uint64_t*)take((size_t)nc.tiles * sizeof(uint64_t));
-    bufs = (BufPair*)take((size_t)nc.bufs * sizeof(BufPair));
     stage_keys = (int64_t*)take((size_t)cap_stats * 2 * sizeof(int64_t));
     pending = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
     done_stage = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
@@ -272,7 +272,6 @@ StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_
     a.fin[k] = ws.fin[k];
   }
   a.status = ws.status;
-  a.bufs = ws.bufs;
   a.pivot_out = pivot_out;
   a.pending = nullptr;
   a.done_stage = nullptr;
@@ -443,16 +442,23 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       it = g_graphs.end();
     }
     if (it == g_graphs.end()) {
+      // Record on a private stream (the caller's may be the legacy null
+      // stream, which cannot be captured); the graph is launched on the
+      // caller's stream.
+      if (!ws.capture) KSORT_HIP(hipStreamCreateWithFlags(&ws.capture, hipStreamNonBlocking));
       hipGraph_t g = nullptr;
-      KSORT_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      KSORT_HIP(hipStreamBeginCapture(ws.capture, hipStreamCaptureModeThreadLocal));
+      const hipStream_t user = ws.stream;
+      ws.stream = ws.capture;
       int crc = enqueue_prologue(ws, *v, dtype, d_data, n, d_offsets, nseg, d_pivots);
       for (int s = 0; s < batch && crc == KSORT_OK; ++s)
         crc = launch_stage(ws, *v, stage_args(ws, *v, s, d_pivots, 1, 1), grid);
       if (crc == KSORT_OK) {
-        hipError_t e = hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, stream);
+        hipError_t e = hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, ws.capture);
         if (e != hipSuccess) crc = hip_fail(e, "hipMemcpyAsync(flags)");
       }
-      hipError_t e = hipStreamEndCapture(stream, &g);
+      ws.stream = user;
+      hipError_t e = hipStreamEndCapture(ws.capture, &g);
       if (crc) {
         if (g) (void)hipGraphDestroy(g);
         return crc;
@@ -476,7 +482,7 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
     if (rc) return rc;
   }
 
-  std::vector<hipEvent_t> evs;
+  size_t nev = 0;  // events of the pool used by this call
   std::vector<int> ev_stage;
   for (;;) {
     if (graphed) {
@@ -489,14 +495,15 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
           KSORT_HIP(hipGetLastError());
         }
         if (prof) {
-          hipEvent_t e0, e1;
-          KSORT_HIP(hipEventCreate(&e0));
-          KSORT_HIP(hipEventCreate(&e1));
-          KSORT_HIP(hipEventRecord(e0, stream));
+          while (ws.events.size() < nev + 2) {
+            hipEvent_t e;
+            KSORT_HIP(hipEventCreate(&e));
+            ws.events.push_back(e);
+          }
+          KSORT_HIP(hipEventRecord(ws.events[nev], stream));
           rc = launch_stage(ws, *v, stage_args(ws, *v, stage, d_pivots, 1, 1), grid);
-          KSORT_HIP(hipEventRecord(e1, stream));
-          evs.push_back(e0);
-          evs.push_back(e1);
+          KSORT_HIP(hipEventRecord(ws.events[nev + 1], stream));
+          nev += 2;
           ev_stage.push_back(stage);
         } else {
           rc = launch_stage(ws, *v, stage_args(ws, *v, stage, d_pivots, 1, 1), grid);
@@ -522,7 +529,7 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
     KSORT_HIP(hipMemcpy(sk.data(), ws.stage_keys, sk.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
     for (size_t k = 0; k < ev_stage.size(); ++k) {
       float ms = 0.f;
-      KSORT_HIP(hipEventElapsedTime(&ms, evs[2 * k], evs[2 * k + 1]));
+      KSORT_HIP(hipEventElapsedTime(&ms, ws.events[2 * k], ws.events[2 * k + 1]));
       ksort_level_record r;
       memset(&r, 0, sizeof r);
       r.call = call;
@@ -537,7 +544,6 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       r.grid = grid;
       profile_push(r);
     }
-    for (auto e : evs) (void)hipEventDestroy(e);
   }
   return KSORT_OK;
 }

@@ -6,20 +6,24 @@
 
 namespace ksort {
 
-// A segment of one stage.  Live segments (len > cutoff) carry first_tile;
-// finish segments (1 <= len <= cutoff) do not use it.
+// A segment of one stage (48 bytes).  Live segments (len > cutoff) carry
+// first_tile; finish segments (1 <= len <= cutoff) do not use it.  Every
+// segment carries the two buffers of its array, so a tile or a finish task
+// needs one descriptor load before it can load keys.
 struct Seg {
   int64_t left;        // index of the segment's first key in its buffers
   int64_t len;         // number of keys
+  void* data;          // the caller's array; final keys are written here
+  void* scratch;       // ping-pong partner with the same extent
   int32_t root;        // >= 0: the segment is a whole input array, index of its pivot slot
-  int32_t buf;         // index of the buffer pair holding the keys
-  int32_t parity;      // 0: keys are in bufs[buf].data, 1: in bufs[buf].scratch
+  int32_t buf;         // request slot (completion accounting of the server)
+  int32_t parity;      // 0: keys are in data, 1: in scratch
   int32_t first_tile;  // first partition ticket of the segment's tiles
 };
 
 struct BufPair {
-  void* data;     // the caller's array; final keys are written here
-  void* scratch;  // ping-pong partner with the same extent
+  void* data;
+  void* scratch;
 };
 
 // Per-stage counters; stage s appends its children to ctr[(s + 1) % 3] and
@@ -35,7 +39,7 @@ struct StageCtr {
 struct Flags {
   int32_t last_active;  // highest stage index that has work
   int32_t err;          // invalid input segment seen by the init kernel
-  int32_t overflow;     // sticky copy of any StageCtr::overflow
+  int32_t overflow;     // a device consistency check failed (code)
   int32_t pad;
 };
 
@@ -45,10 +49,9 @@ struct StageArgs {
   int32_t* tilemap[2];    // partition ticket -> live slot, by stage parity
   Seg* fin[2];            // finish lists by stage parity
   uint64_t* status;       // look-back words, one per partition ticket
-  const BufPair* bufs;
   int64_t* pivot_out;     // per root (nullable)
-  int32_t* pending;       // per buffer pair: outstanding segments (nullable)
-  int32_t* done_stage;    // per buffer pair: stage at which pending hit 0 (nullable)
+  int32_t* pending;       // per request slot: outstanding segments (nullable)
+  int32_t* done_stage;    // per request slot: stage at which pending hit 0 (nullable)
   Flags* flags;
   int64_t* stage_keys;    // [cap_stats][2]: keys partitioned, keys finished (nullable)
   int32_t cap_live, cap_tiles, cap_fin, cap_stats;
@@ -63,8 +66,8 @@ struct StageArgs {
 // level, caller-given segments) into the lists of one stage.
 struct InitArgs {
   StageArgs sa;              // lists, counters and flags of the run
-  BufPair pair;              // written to bufs[buf]
-  int32_t buf;               // buffer pair of these arrays
+  BufPair pair;              // the arrays' buffers
+  int32_t buf;               // request slot of these arrays
   int32_t root_base;         // pivot slot of array 0
   int64_t n;                 // extent of the caller's array
   const int64_t* offsets;    // nseg + 1 array offsets (sort modes), or null
