@@ -107,16 +107,15 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
   return v;
 }
 
-// Value x of every lane goes to lane dst (the lanes' dst form a permutation).
-__device__ __forceinline__ int lane_push(int x, int dst) { return __builtin_amdgcn_ds_permute(dst << 2, x); }
-__device__ __forceinline__ float lane_push(float x, int dst) {
-  return __int_as_float(__builtin_amdgcn_ds_permute(dst << 2, __float_as_int(x)));
+// The value v holds in lane j (j wave-uniform).
+__device__ __forceinline__ float lane_read(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
 }
-__device__ __forceinline__ double lane_push(double x, int dst) {
-  const uint64_t u = (uint64_t)__double_as_longlong(x);
-  const int lo = __builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)u);
-  const int hi = __builtin_amdgcn_ds_permute(dst << 2, (int)(uint32_t)(u >> 32));
-  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+__device__ __forceinline__ double lane_read(double v, int j) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), j);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // Look-back word: count in bits 0..39, flag in 40..41, epoch in 42..63.
@@ -129,6 +128,7 @@ __device__ __forceinline__ uint64_t status_word(uint32_t epoch, uint64_t flag, u
 // ---------------------------------------------------------------------------
 // work items
 
+constexpr int kTaskUnclaimed = -1;  // the block has not claimed its next ticket yet
 constexpr int kTaskNone = 0;
 constexpr int kTaskTile = 1;
 constexpr int kTaskFinish = 2;
@@ -136,7 +136,7 @@ constexpr int kTaskFinish = 2;
 struct Task {
   Seg seg;
   int32_t kind;
-  int32_t t;  // the ticket
+  int32_t t;  // partition tiles: index into the stage's tile map (look-back slot)
 };
 
 __device__ __forceinline__ void load_seg(Seg* d, const KS_GLOBAL Seg* s) {
@@ -167,16 +167,35 @@ __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, in
   const int par = a.stage & 1;
   const int32_t t = add_agent(&cur->ticket, 1);
   out->t = t;
-  if (t < ntiles) {
-    const int32_t slot = ((const KS_GLOBAL int32_t*)a.tilemap[par])[t];
+  // Finish tasks take the first tickets: they never wait on anyone and take
+  // longer than a tile, so starting them first keeps them off the end of the
+  // stage.  Partition tiles follow in segment order (the look-back relies on
+  // a tile's predecessors holding lower tickets).
+  const int32_t nfin = nwork - ntiles;
+  if (t < nfin) {
+    load_seg(&out->seg, (const KS_GLOBAL Seg*)a.fin[par] + t);
+    out->kind = kTaskFinish;
+  } else if (t < nwork) {
+    const int32_t tt = t - nfin;
+    const int32_t slot = ((const KS_GLOBAL int32_t*)a.tilemap[par])[tt];
     load_seg(&out->seg, (const KS_GLOBAL Seg*)a.live[par] + slot);
     out->kind = kTaskTile;
-  } else if (t < nwork) {
-    load_seg(&out->seg, (const KS_GLOBAL Seg*)a.fin[par] + (t - ntiles));
-    out->kind = kTaskFinish;
+    out->t = tt;
   } else {
     out->kind = kTaskNone;
   }
+}
+
+// Finish work claims its successor early, hiding the claim behind the sort,
+// but only while finish tickets remain: a partition tile is claimed only when
+// the block is free to load it, because every later tile of its segment waits
+// for its count in the look-back.
+__device__ __forceinline__ void claim_early(const StageArgs& a, StageCtr* cur, int32_t ntiles, int32_t nwork,
+                                            Task* out) {
+  if (ld_agent(&cur->ticket) < nwork - ntiles)
+    fetch_task(a, cur, ntiles, nwork, out);
+  else
+    out->kind = kTaskUnclaimed;
 }
 
 // A work item read from LDS, with every field wave-uniform.
@@ -375,8 +394,8 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
 // partition work: one tile of one live segment
 
 template <typename T, int BLOCK, int ITEMS>
-__device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, BLOCK, ITEMS>& sm,
-                               StageCtr* cur, int32_t ntiles, int32_t nwork, Task* next) {
+__device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, BLOCK, ITEMS>& sm, StageCtr* cur,
+                               int32_t ntiles, int32_t nwork, Task* next) {
   constexpr int NW = BLOCK / kWave;
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int NC = ITEMS * NW;                 // per-(item, wave) counts
@@ -476,9 +495,6 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
     }
   }
   __syncthreads();
-  // this tile no longer holds anyone up: claim and resolve the next ticket,
-  // hidden behind the scatter below
-  if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
 
   // a4: scatter from registers.  Smaller keys fill [left, i-1] upward, the
   // others fill [i+1, right] downward.  The runs always lie inside the
@@ -489,6 +505,7 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
   const int64_t right = left + len - 1;
   if (xlt < 0 || xge < 0 || xlt + tot_lt > len - 1 || xge + tot_ge > len - 1) {
     if (tid == 0) st_agent(&a.flags->overflow, 2);
+    if (tid == BLOCK - 1) next->kind = kTaskNone;
     return;
   }
   T* dlt = out + left + xlt;                  // first slot of this tile's smaller keys
@@ -515,6 +532,8 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
 
   // a5/a6: the segment's last tile places the key and emits the two sides.
   if (o + cnt == len) emit_children<T, TILE>(a, sm.em_slot, sm.em_first, sm.em_nt, tk, xlt + tot_lt, key);
+  // the block is free: claim its next work item
+  if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
 }
 
 // ---------------------------------------------------------------------------
@@ -522,47 +541,34 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
 
 constexpr int kSmall = kWave;  // sub-segments of at most this many keys finish in registers
 
-// K-sort of in[0 .. L-1] (1 <= L <= 64) by one wave, in registers, one key
-// per lane; lane j holds position j and (sl, sL) is the sub-segment of that
-// position.  The sorted keys are written to out[0 .. L-1].
+// Sorts in[0 .. L-1] (1 <= L <= 64) into out[0 .. L-1] with one wave, one key
+// per lane, by placing every key at its rank: the number of keys smaller than
+// it plus the number of equal keys before it.  For keys under a total order
+// (no NaN, one sign of zero) this is the one ascending arrangement, so it is
+// exactly what further K-sort levels would produce on the sub-segment, with
+// no chain of dependent cross-lane steps.  The rank of the first key is the
+// segment's Step-4 pivot offset (no key before it can tie), written to
+// *pivot_slot when it is given.
 template <typename T, typename In>
-__device__ void wave_ksort(const In* in, T* out, int L, int64_t* pivot_slot, int64_t pivot_bias) {
+__device__ void wave_rank_sort(const In* in, T* out, int L, int64_t* pivot_slot, int64_t pivot_bias) {
   const int lane = lane_id();
   T v = lane < L ? (T)in[lane] : T(0);
-  int sl = 0, sL = lane < L ? L : 0;
-  bool first = pivot_slot != nullptr;
-  for (;;) {
-    const bool act = sL >= 2;
-    if (__ballot(act) == 0) break;
-    const T key = __shfl(v, sl, kWave);
-    const bool lt = act && lane != sl && !(key <= v);
-    const uint64_t m = __ballot(lt);
-    const int pre = mbcnt(m);
-    const int base_pre = __shfl(pre, sl, kWave);
-    const uint64_t range = (sL >= 64 ? ~0ull : ((1ull << sL) - 1)) << sl;
-    const int tot = __popcll(m & range);  // smaller keys in the sub-segment
-    int dest = lane, nl = sl, nL = sL;
-    if (act) {
-      if (lane == sl) {
-        dest = sl + tot;
-        nl = dest;
-        nL = 1;
-        if (first) *pivot_slot = pivot_bias + tot;
-      } else if (lt) {
-        dest = sl + (pre - base_pre);
-        nL = tot;
-      } else {
-        dest = sl + tot + 1 + (lane - sl - 1 - (pre - base_pre));
-        nl = sl + tot + 1;
-        nL = sL - tot - 1;
-      }
+  asm volatile("" : "+v"(v));
+  int rank = 0;
+  int j = 0;
+  for (; j + 4 <= L; j += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T b = lane_read(v, j + u);
+      rank += (b < v) | ((b <= v) & (j + u < lane));
     }
-    first = false;
-    v = lane_push(v, dest);
-    sl = lane_push(nl, dest);
-    sL = lane_push(nL, dest);
   }
-  if (lane < L) gst<T>(out, (uint32_t)(lane * sizeof(T)), v);
+  for (; j < L; ++j) {
+    const T b = lane_read(v, j);
+    rank += (b < v) | ((b <= v) & (j < lane));
+  }
+  if (lane < L) gst<T>(out, (uint32_t)(rank * sizeof(T)), v);
+  if (pivot_slot && lane == 0) *pivot_slot = pivot_bias + rank;
 }
 
 // One partition of in[s .. s+L-1] into out[s .. s+L-1] by one wave (Steps
@@ -618,16 +624,14 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
   const int64_t pivot_bias = a.pivot_relative ? 0 : left;
   if (len < 1 || len > CUT) {  // never produced by the emitters; guards the LDS arrays
     if (tid == 0) st_agent(&a.flags->overflow, 3);
-    if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
+    if (tid == BLOCK - 1) next->kind = kTaskNone;
     return;
   }
 
   if (len <= kSmall) {
-    // one wave finishes the whole segment in registers (a single key is its
-    // own first pivot)
-    if (tid < kWave) wave_ksort<T>((const KS_GLOBAL T*)src, dst, len, pivot_slot, pivot_bias);
-    if (tid == 0 && len == 1 && pivot_slot) *pivot_slot = pivot_bias;
-    if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
+    // one wave finishes the whole segment in registers
+    if (tid < kWave) wave_rank_sort<T>((const KS_GLOBAL T*)src, dst, len, pivot_slot, pivot_bias);
+    if (tid == BLOCK - 1) claim_early(a, cur, ntiles, nwork, next);
   } else {
     {
       // all loads in flight before the first LDS store
@@ -648,30 +652,34 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
       sm.outstanding = 1;
     }
     __syncthreads();
-    if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
-    // Each wave takes sub-segments from the queue until none is outstanding.
-    // Every branch of this loop is taken on a wave-uniform value (read with
-    // readfirstlane before the test): the lanes must stay together for the
-    // cross-lane operations inside, and a branch on a per-lane load would
-    // let the compiler split them (it may route lanes through different loop
-    // exits when it cannot prove a condition uniform).
+    if (tid == BLOCK - 1) claim_early(a, cur, ntiles, nwork, next);
+    // Each wave takes sub-segments from the queue until none is outstanding;
+    // after a partition it keeps the smaller side for itself and queues the
+    // other.  Every branch of this loop is taken on a wave-uniform value
+    // (read with readfirstlane before the test): the lanes must stay
+    // together for the cross-lane operations inside, and a branch on a
+    // per-lane load would let the compiler split them (it may route lanes
+    // through different loop exits when it cannot prove a condition uniform).
+    uint32_t e = 0;
     for (;;) {
-      int idx = 0;
-      if (lane == 0) idx = atomicAdd(&sm.q_head, 1);
-      idx = uniform(idx);
-      uint32_t e = 0;
-      for (;;) {
-        e = (uint32_t)uniform(
-            (int)__hip_atomic_load(&sm.q[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
-        if (e != 0) break;
-        if (uniform(ld_group(&sm.outstanding)) == 0) break;
-        __builtin_amdgcn_s_sleep(1);
+      if (e == 0) {
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(&sm.q_head, 1);
+        idx = uniform(idx);
+        for (;;) {
+          e = (uint32_t)uniform((int)__hip_atomic_load(&sm.q[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+          if (e != 0) break;
+          if (uniform(ld_group(&sm.outstanding)) == 0) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        if (e == 0) break;  // everything is done
+        asm volatile("" ::: "memory");  // the side's keys are read only after its entry
       }
-      if (e == 0) break;  // everything is done
       const int p = (e >> 1) & 1, s = (e >> 2) & 0xfff, L = (int)(e >> 14);
       int pushed = 0;
+      uint32_t keep = 0;
       if (L <= kSmall) {
-        wave_ksort<T>(sm.buf[p] + s, dst + s, L, nullptr, 0);
+        wave_rank_sort<T>(sm.buf[p] + s, dst + s, L, nullptr, 0);
       } else {
         const T key = sm.buf[p][s];
         const int cl = wave_partition<T>(sm.buf[p], sm.buf[p ^ 1], s, L, key);
@@ -681,26 +689,28 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
           if (pivot_slot && L == len) *pivot_slot = pivot_bias + cl;
         }
         // Steps 5-6 on the two sides (a side of one key is final)
-        const int cs[2] = {s, s + cl + 1};
-        const int cn[2] = {cl, cg};
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          if (cn[c] == 1) {
-            if (lane == 0) gst<T>(dst, (uint32_t)(cs[c] * sizeof(T)), sm.buf[p ^ 1][cs[c]]);
-          } else if (cn[c] >= 2) {
-            if (lane == 0) {
-              const int qi = atomicAdd(&sm.q_tail, 1);
-              // release: the side's keys, written above, are seen by the wave that takes it
-              __hip_atomic_store(&sm.q[qi], q_entry(cs[c], cn[c], p ^ 1), __ATOMIC_RELEASE,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-            ++pushed;
-          }
+        if (cl == 1 && lane == 0) gst<T>(dst, (uint32_t)(s * sizeof(T)), sm.buf[p ^ 1][s]);
+        if (cg == 1 && lane == 0) gst<T>(dst, (uint32_t)((s + cl + 1) * sizeof(T)), sm.buf[p ^ 1][s + cl + 1]);
+        const uint32_t el = cl >= 2 ? q_entry(s, cl, p ^ 1) : 0u;
+        const uint32_t eg = cg >= 2 ? q_entry(s + cl + 1, cg, p ^ 1) : 0u;
+        pushed = (el != 0) + (eg != 0);
+        // keep the smaller side, queue the other
+        const bool keep_lt = el != 0 && (eg == 0 || cl <= cg);
+        keep = keep_lt ? el : eg;
+        const uint32_t give = keep_lt ? eg : el;
+        if (give != 0 && lane == 0) {
+          // the side's keys (written by this wave) are in LDS before its entry
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+          const int qi = atomicAdd(&sm.q_tail, 1);
+          __hip_atomic_store(&sm.q[qi], give, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
-      // the writes of this wave's new entries come before this update
-      if (lane == 0)
-        __hip_atomic_fetch_add(&sm.outstanding, pushed - 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      // new entries are written before this update
+      if (lane == 0) {
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        __hip_atomic_fetch_add(&sm.outstanding, pushed - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      e = (uint32_t)uniform((int)keep);
     }
     __syncthreads();
   }
@@ -708,6 +718,7 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
     const int32_t old = add_agent(a.pending + tk.buf, -1);
     if (old - 1 == 0 && a.done_stage) st_agent(a.done_stage + tk.buf, a.stage);
   }
+  if (tid == BLOCK - 1 && next->kind == kTaskUnclaimed) fetch_task(a, cur, ntiles, nwork, next);
 }
 
 // ---------------------------------------------------------------------------
