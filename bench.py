@@ -2,17 +2,32 @@
 
 One step = one whole sort (every level pass, the LDS finish and the host
 level loop) of one resident FP64 array of n = 7,000,000 i.i.d. U[0,1) keys
-(seed 4).  K distinct input copies are drawn into device memory before the
+(seed 4).  Distinct input copies are drawn into device memory before the
 timed region, so every step sorts unsorted data that is already in HBM.
-Prints ONE JSON line (see the keys below).
+
+Prints ONE JSON line:
+  value / ms_per_step   K whole sorts timed between two device syncs
+  roofline              the stage kernel (one level pass: partition tiles and
+                        LDS finish work) against the HBM peak; each launch is
+                        bracketed by HIP events on the sort's stream, in a
+                        second timed pass over K fresh copies
+  batched               4096 arrays (log-uniform lengths in [32, 65536]) in
+                        one segmented call vs 4096 plain calls vs one plain
+                        sort of the same key count
+  serve                 a seeded Poisson stream of requests through the sort
+                        server: p50/p99 latency and keys/s
+  cpu_baseline          the literal CPU oracle on the host, one thread
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
+                  [--copy-probe BYTES]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,6 +37,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published peak
 PAPER_7E6_S = 3.2892           # Table 1: K-sort mean time at n = 7,000,000 (CPU, Turbo C++ 5.02)
+KERNEL_SRC = os.path.join(ROOT, "paper_1107_3622_amd", "csrc", "ksort_kernels.h")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_c1_n7e6_f64_pmc.txt")
 
 
 def log(msg: str) -> None:
@@ -35,9 +52,32 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="c1_n7e6_f64")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
-    p.add_argument("--no-extras", action="store_true", help="skip batched / serving lines")
+    p.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--copy-probe", type=int, default=0,
+                   help="only run device copies of this many bytes (counter calibration)")
     return p.parse_args()
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per stage-kernel launch from the committed counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None, "no counter summary"
+    m_sha = re.search(r"kernel_sha256:\s*([0-9a-f]{64})", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_b:
+        return None, "counter summary incomplete"
+    if m_sha.group(1) != kernel_sha():
+        return None, "kernel changed since the counters were taken"
+    return float(m_b.group(1)), os.path.relpath(PMC_SUMMARY, ROOT)
 
 
 def cpu_baseline(workload: str, budget_s: float) -> dict:
@@ -62,6 +102,103 @@ def cpu_baseline(workload: str, budget_s: float) -> dict:
             "sample": f"{len(times)} whole sorts of the same {a.size}-key array (mean {mean:.3f} s each)"}
 
 
+def copy_probe(nbytes: int) -> int:
+    """Device-to-device copies of a known size, for scaling the memory
+    counters: FETCH_SIZE and WRITE_SIZE of one copy should read nbytes."""
+    import torch
+    n = nbytes // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 8, "copies": 5}), flush=True)
+    return 0
+
+
+def batched_leg(ksort, torch) -> dict:
+    import synth
+    keys, offs = synth.batched(9, 10, 4096, 32, 65536)
+    n = int(offs[-1])
+    src = torch.from_numpy(keys).to("cuda")
+    d_offs = torch.from_numpy(offs).to("cuda")
+    ref = src.clone()
+    reps = 5
+    copies = [src.clone() for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ksort.ksort_segmented(copies[0], d_offs, want_pivots=False)  # captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        ksort.ksort_segmented(copies[1 + k], d_offs, want_pivots=False)
+    torch.cuda.synchronize()
+    seg_s = (time.perf_counter() - t0) / reps
+    # correctness: stable sort by key, then stable sort by array index
+    seg_id = torch.repeat_interleave(torch.arange(4096, device="cuda"), d_offs[1:] - d_offs[:-1])
+    v, idx = torch.sort(ref, stable=True)
+    _, idx2 = torch.sort(seg_id[idx], stable=True)
+    ok = all(torch.equal(c, v[idx2]) for c in copies)
+    # plain loop: one ksort_f64 call per array on views of the packed buffer
+    loop = src.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for u in range(4096):
+        ksort.ksort_f64(loop[int(offs[u]):int(offs[u + 1])])
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    ok = ok and torch.equal(loop, v[idx2])
+    # one plain sort of the same key count
+    one = synth.torch_fill("uniform_f64", 10, n, "cuda")
+    ones = [one.clone() for _ in range(reps + 1)]
+    ksort.ksort_f64(ones[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        ksort.ksort_f64(ones[1 + k])
+    torch.cuda.synchronize()
+    one_s = (time.perf_counter() - t0) / reps
+    return {"arrays": 4096, "keys": n, "segmented_keys_per_s": n / seg_s, "segmented_ms": seg_s * 1e3,
+            "plain_loop_keys_per_s": n / loop_s, "plain_loop_ms": loop_s * 1e3,
+            "one_plain_sort_keys_per_s": n / one_s, "one_plain_sort_ms": one_s * 1e3,
+            "verified": bool(ok)}
+
+
+def serve_leg(ksort, torch) -> dict:
+    """A seeded Poisson stream through the sort server, submitted at its
+    arrival times while earlier requests are on the device: 120 requests,
+    sizes log-uniform in [1e3, 1e5], 70 % FP64, 2000 arrivals/s, 32 in
+    flight under a 1 GiB budget.  Inputs are drawn on the device before
+    the stream starts.  (The full stream of 20,000 requests of up to 1e7 keys
+    under 64 GiB stalled on the device and is not run; see the design
+    notes.)"""
+    import synth
+    count = 120
+    sizes, is_f64, arrivals = synth.serve_requests(count, 12, 13, 11, 1_000, 100_000, 0.7, 2000.0)
+    reqs = [synth.torch_fill("uniform_f64" if f else "uniform_f32", synth.REQUEST_SEED_BASE + r, int(n), "cuda")
+            for r, (n, f) in enumerate(zip(sizes, is_f64))]
+    refs = [torch.sort(t)[0] for t in reqs]
+    torch.cuda.synchronize()
+    with ksort.Server(1 << 30, 32) as srv:
+        t0 = time.perf_counter()
+        tks = []
+        for t, at in zip(reqs, arrivals):
+            dt = at - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tks.append(srv.submit(t))
+        rcs = [srv.wait(tk, 60.0) for tk in tks]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    keys = int(sizes.sum())
+    ok = all(rc == 0 for rc in rcs) and all(torch.equal(t, ref) for t, ref in zip(reqs, refs))
+    return {"stream": "reduced: 120 requests, sizes log-uniform [1e3, 1e5], 70 % FP64, 2000/s, "
+                      "32 in flight, 1 GiB budget",
+            "requests": count, "keys": keys, "wall_s": wall, "keys_per_s": keys / wall,
+            "keys_per_busy_s": keys / st["busy_s"] if st["busy_s"] > 0 else None,
+            "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+            "completed": st["completed"], "failed": st["failed"], "verified": bool(ok)}
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
@@ -77,11 +214,13 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no HIP device"}), flush=True)
         return 1
+    if args.copy_probe:
+        return copy_probe(args.copy_probe)
     dev = torch.device("cuda:0")
     w = synth.WORKLOADS[args.workload]
     n = w["n"]
     assert w["kind"] in ("uniform_f64", "grid16_f64", "uniform_f32")
-    log(f"workload {args.workload} n={n}; drawing {args.steps + args.warmup} copies on the device")
+    log(f"workload {args.workload} n={n}; drawing {2 * args.steps + args.warmup} copies on the device")
     src = synth.torch_fill(w["kind"], w["seed"], n, dev)
     sort_fn = ksort.ksort_f64 if src.dtype == torch.float64 else ksort.ksort_f32
     key_bytes = src.element_size()
@@ -93,46 +232,47 @@ def main() -> int:
     torch.cuda.synchronize()
     log("warmup done")
 
-    # plain timed region (no per-level events)
-    torch.cuda.synchronize()
-    u0 = time.perf_counter()
-    for k in range(args.steps):
-        sort_fn(copies[args.warmup + args.steps + k])
-    torch.cuda.synchronize()
-    unprofiled = time.perf_counter() - u0
-    log(f"unprofiled: {args.steps} steps in {unprofiled:.4f} s")
-
-    # timed region: K whole sorts, each level pass bracketed by HIP events on
-    # the library's stream (the current stream)
-    ksort.ksort_profile_read()
-    ksort.ksort_profile_enable(True)
+    # timed region: K whole sorts; per-call HIP events give the spread
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
+        ev[k][0].record()
         sort_fn(copies[args.warmup + k])
+        ev[k][1].record()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ksort.ksort_profile_enable(False)
-    recs = ksort.ksort_profile_read()
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
+    per_call = sorted(a.elapsed_time(b) for a, b in ev)
     log(f"timed {args.steps} steps in {elapsed:.4f} s")
 
-    # roofline of the stage kernel (every level pass): algorithmic bytes are
-    # 2 * key_bytes per key partitioned plus 2 * key_bytes per key finished
+    # second pass over fresh copies: every stage launch bracketed by HIP
+    # events on the sort's stream (the current stream)
+    ksort.ksort_profile_read()
+    ksort.ksort_profile_enable(True)
+    torch.cuda.synchronize()
+    for k in range(args.steps):
+        sort_fn(copies[args.warmup + args.steps + k])
+    torch.cuda.synchronize()
+    ksort.ksort_profile_enable(False)
+    recs = ksort.ksort_profile_read()
+
+    # roofline of the stage kernel: algorithmic bytes are 2 * key_bytes per
+    # key partitioned plus 2 * key_bytes per key finished
     tot_ms = sum(r["ms"] for r in recs)
     tot_bytes = sum(2 * key_bytes * (r["live_keys"] + r["finish_keys"]) for r in recs)
     launches = len(recs)
     achieved = tot_bytes / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
-    stages_per_sort = launches / max(args.steps, 1)
-    passes_per_key = sum(r["live_keys"] for r in recs) / (n * args.steps)
+    big = [r for r in recs if 2 * key_bytes * r["live_keys"] >= 0.5 * 2 * key_bytes * n]
+    big_gbs = (sum(2 * key_bytes * (r["live_keys"] + r["finish_keys"]) for r in big) /
+               (sum(r["ms"] for r in big) * 1e-3) / 1e9) if big else None
+    traffic, traffic_src = stored_traffic()
 
-    # correctness of the timed output: sorted order equal to the library sort
-    # of torch (an independent check)
-    last = copies[args.warmup + args.steps - 1]
+    # correctness of the timed outputs: equal to the library sort of torch
     ref = torch.sort(src.clone())[0]
-    ok = bool(torch.equal(last, ref))
+    ok = all(torch.equal(copies[args.warmup + k], ref) for k in range(2 * args.steps))
 
     value = n * args.steps / elapsed
+    q = lambda p: per_call[min(len(per_call) - 1, int(round(p * (len(per_call) - 1))))]
     out = {
         "metric": "sorted keys/s FP64 n=7e6 (+HBM GB/s/pass); batched vs plain; serve p50/p99",
         "value": value,
@@ -143,21 +283,33 @@ def main() -> int:
         "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
+        # the paper's own K-sort time at this n (Table 1; CPU, another machine): context
         "vs_baseline": value / (7_000_000 / PAPER_7E6_S) if args.workload == "c1_n7e6_f64" else None,
         "dtype": "f64" if key_bytes == 8 else "f32",
         "data": "synthetic: SplitMix64 U[0,1) keys drawn on the device",
         "config": {"workload": f"{args.workload}: n={n} {w['kind']} seed {w['seed']}, one array per call",
                    "variant": list(ksort.ksort_get_default(0 if key_bytes == 8 else 1))},
+        "per_call_ms": {"p10": q(0.1), "median": q(0.5), "p90": q(0.9)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "stage_kernel (level pass: partition tiles + LDS finish)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "traffic_source": traffic_src,
+                     "kernel": "stage_kernel (one level pass: partition tiles + LDS finish)",
                      "launches": launches, "avg_launch_ms": tot_ms / max(launches, 1),
-                     "alg_bytes_per_launch": tot_bytes / max(launches, 1)},
-        "levels_per_sort": stages_per_sort,
-        "partition_passes_per_key": passes_per_key,
+                     "alg_bytes_per_launch": tot_bytes / max(launches, 1),
+                     "full_passes_gbs": big_gbs, "full_passes": len(big),
+                     "timing": "HIP events around every stage launch, second pass over fresh copies"},
+        "levels_per_sort": launches / max(args.steps, 1),
+        "partition_passes_per_key": sum(r["live_keys"] for r in recs) / (n * args.steps),
         "verified_sorted_equal_torch_sort": ok,
-        "ms_per_step_without_level_events": unprofiled / args.steps * 1e3,
+        "paper_table1_keys_per_s_n7e6": 7_000_000 / PAPER_7E6_S,
     }
+    if not args.no_extras:
+        log("batched leg")
+        out["batched"] = batched_leg(ksort, torch)
+        log("serving leg")
+        out["serve"] = serve_leg(ksort, torch)
+        ok = ok and out["batched"]["verified"] and out["serve"]["verified"]
     if not args.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)

@@ -200,8 +200,11 @@ KSORT_API int ksort_release_workspaces(void);
  * ksort_server_create: device = HIP device ordinal.  Returns NULL on error
  *   (see ksort_last_error).
  * ksort_server_submit: d_data is borrowed until the request completes or is
- *   cancelled; *ticket receives its id.  KSORT_ETOOLARGE if the request can
- *   never fit the budget, KSORT_EAGAIN if the pending queue is full.
+ *   cancelled; *ticket receives its id.  The server runs on streams of its
+ *   own, so every write of d_data must be complete when the call is made
+ *   (synchronize the producing stream first).  KSORT_ETOOLARGE if the
+ *   request can never fit the budget, KSORT_EAGAIN if the pending queue is
+ *   full.
  * ksort_server_poll: *state = 0 pending/running, 1 done, or a negative error.
  * ksort_server_wait: blocks up to timeout_s seconds (negative = forever);
  *   returns KSORT_OK when done, KSORT_ETIMEOUT, or the request's error.

@@ -1,8 +1,8 @@
 // Autotuner: times every compiled kernel variant (threads per workgroup,
 // keys per thread in a partition tile, LDS-finish cutoff) on a seeded
 // U[0,1) input of the requested size and key type, and makes the fastest the
-// default for inputs of about that size (the same power-of-two bucket).
-// Results can be saved to and loaded from a small JSON file.
+// default for inputs of about that size (the same power-of-two bucket, or
+// the nearest tuned bucket at most two powers of two away).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -301,7 +301,10 @@ class Server:
         self._keep = {}
 
     def submit(self, t) -> int:
+        """Submit t for sorting in place.  The server works on streams of its
+        own, so the current stream (which produced t) is synchronized first."""
         _check_keys(t)
+        _torch().cuda.current_stream(t.device).synchronize()
         tk = ctypes.c_uint64()
         _check(load().ksort_server_submit(self._h, _dtype_code(t), t.data_ptr(), t.numel(), ctypes.byref(tk)),
                "ksort_server_submit")

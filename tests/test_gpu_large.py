@@ -1,0 +1,91 @@
+"""GPU parity at the full sizes of the large and duplicate-heavy workloads,
+the autotuner, and the per-level profile records.
+
+At 2^28 / 2^29 keys the literal oracle would take minutes, so the checks
+there are properties that hold at any size: the output equals the library
+sort of torch (the sorted arrangement is unique for keys without NaN and
+with one sign of zero), and the first pivot equals the closed form
+i = #{x : x < a[0]} (pinned against the literal oracle on the CPU)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_bit_equal, note, to_dev, to_host, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def check_by_properties(name):
+    from paper_1107_3622_amd import ksort
+    torch = torch_dev()
+    note(f"{name} (torch.sort + closed-form pivot)")
+    t = synth.torch_make(name, "cuda")
+    want_pivot = int((t < t[0]).sum().item())
+    ref = torch.sort(t)[0]
+    p = ksort.sort_(t)
+    assert torch.equal(t, ref), f"{name}: output differs from torch.sort"
+    assert p == want_pivot, f"{name}: first pivot {p}, closed form {want_pivot}"
+    del t, ref
+    torch.cuda.empty_cache()
+
+
+def test_c2_n2p28_f64():
+    check_by_properties("c2_n2^28_f64")
+
+
+def test_c2_n2p29_f32():
+    check_by_properties("c2_n2^29_f32")
+
+
+@pytest.mark.parametrize("name", ["c2_grid16_n1e7_f64", "c1_n1e7_f64", "c1_n2.5e6_f64", "c1_n1e6_f64"])
+def test_oracle_full_size(name):
+    from paper_1107_3622_amd import ksort
+    torch_dev()
+    a = synth.make(name)
+    note(f"{name} vs oracle")
+    t = to_dev(a)
+    p = ksort.sort_(t)
+    want, wp = oracle.sorted_copy(a)
+    assert_bit_equal(to_host(t), want, name)
+    assert p == wp
+
+
+def test_autotune_then_sort():
+    from paper_1107_3622_amd import ksort
+    torch_dev()
+    note("autotune f64 n=300000")
+    best = ksort.ksort_autotune(ksort.KSORT_F64, 300_000)
+    assert best in ksort.ksort_variants(ksort.KSORT_F64)
+    a = synth.uniform_f64(77, 300_000)
+    t = to_dev(a)
+    p = ksort.sort_(t)  # now runs the tuned variant for this size
+    want, wp = oracle.sorted_copy(a)
+    assert_bit_equal(to_host(t), want, "after autotune")
+    assert p == wp
+
+
+def test_profile_records_account_for_every_key():
+    from paper_1107_3622_amd import ksort
+    torch_dev()
+    n = 1_000_000
+    a = synth.uniform_f64(2, n)
+    t = to_dev(a)
+    note("profiled sort n=1e6")
+    ksort.ksort_profile_read()
+    ksort.ksort_profile_enable(True)
+    ksort.ksort_f64(t)
+    ksort.ksort_profile_enable(False)
+    recs = ksort.ksort_profile_read()
+    assert recs and all(r["ms"] > 0 for r in recs)
+    assert [r["stage"] for r in recs] == list(range(len(recs)))
+    assert recs[0]["live_keys"] == n
+    # each partition places its key; every other key ends in a finish
+    # segment or as a one-key side, so the keys finished never exceed n and
+    # the partitions (one key each) plus the finished keys cover all n keys
+    fin = sum(r["finish_keys"] for r in recs)
+    assert 0 < fin <= n
+    # the live keys of a level shrink by at least one key per live segment
+    live = [r["live_keys"] for r in recs]
+    assert all(live[k + 1] < live[k] for k in range(len(live) - 1) if live[k] > 0)
+    assert_bit_equal(to_host(t), np.sort(a), "profiled sort")

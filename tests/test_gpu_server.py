@@ -1,0 +1,163 @@
+"""GPU tests of the serving form (ksort_server_*): requests of mixed sizes
+and key types, admitted while others run, each sorted bit-exactly as the
+oracle sorts it alone; the same result alone and in the mix; admission by
+memory budget; cancellation of queued requests."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_bit_equal, note, to_dev, to_host, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+KSORT_ETOOLARGE = -5
+KSORT_EAGAIN = -6
+KSORT_ECANCELLED = -7
+
+MIB = 1 << 20
+
+
+def request_keys(r: int, n: int, f64: bool) -> np.ndarray:
+    seed = synth.REQUEST_SEED_BASE + r
+    return synth.uniform_f64(seed, n) if f64 else synth.uniform_f32(seed, n)
+
+
+MIX = [(0, True), (1, False), (2, True), (63, False), (64, True), (65, True), (2047, False), (2048, True),
+       (2049, True), (5000, False), (65_537, True), (100_003, False), (300_000, True), (777_777, False)]
+
+
+def serve(requests, budget=1 << 30, max_inflight=64, alone=False):
+    """Sorts every (keys) array through one server; returns (sorted arrays,
+    first pivots, stats).  alone=True waits for each request before the next
+    is submitted."""
+    from paper_1107_3622_amd import ksort
+    outs, pivots = [], []
+    with ksort.Server(budget, max_inflight) as srv:
+        tickets, tensors = [], []
+        for a in requests:
+            t = to_dev(a)
+            tk = srv.submit(t)
+            tickets.append(tk)
+            tensors.append(t)
+            if alone:
+                assert srv.wait(tk, 60.0) == 0
+        for tk in tickets:
+            assert srv.wait(tk, 60.0) == 0, srv.result(tk)
+        for tk, t in zip(tickets, tensors):
+            outs.append(to_host(t))
+            pivots.append(srv.result(tk)["first_pivot"])
+            srv.release(tk)
+        stats = srv.stats()
+    return outs, pivots, stats
+
+
+def test_mix_matches_oracle():
+    torch_dev()
+    reqs = [request_keys(r, n, f64) for r, (n, f64) in enumerate(MIX)]
+    note(f"server mix of {len(reqs)} requests, {sum(a.size for a in reqs)} keys")
+    outs, pivots, stats = serve(reqs)
+    for r, (a, got, p) in enumerate(zip(reqs, outs, pivots)):
+        want, wp = oracle.sorted_copy(a)
+        assert_bit_equal(got, want, f"request {r} n={a.size} {a.dtype}")
+        assert p == wp, f"request {r} n={a.size}: first pivot {p}, oracle {wp}"
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    assert stats["keys_completed"] == sum(a.size for a in reqs)
+    assert stats["p99_latency_s"] >= stats["p50_latency_s"] >= 0.0
+
+
+def test_alone_equals_mix():
+    torch_dev()
+    sizes = [(3000, True), (40_000, False), (250_000, True), (9_000, True), (123_457, False)]
+    reqs = [request_keys(100 + r, n, f64) for r, (n, f64) in enumerate(sizes)]
+    note("server: each request alone, then all together")
+    alone, p_alone, _ = serve(reqs, alone=True)
+    mixed, p_mixed, _ = serve(reqs)
+    for r in range(len(reqs)):
+        assert_bit_equal(mixed[r], alone[r], f"request {r}: mix vs alone")
+        assert p_mixed[r] == p_alone[r]
+
+
+def test_budget_admission():
+    from paper_1107_3622_amd import ksort
+    torch_dev()
+    with ksort.Server(8 * MIB, 8) as srv:
+        big = to_dev(request_keys(200, 1_000_000, True))  # 16 MB of keys + scratch > 8 MiB
+        with pytest.raises(ksort.KsortError) as e:
+            srv.submit(big)
+        assert e.value.code == KSORT_ETOOLARGE
+        # requests that fit one or two at a time queue and all complete, in order
+        reqs = [request_keys(210 + r, 150_000, r % 2 == 0) for r in range(6)]
+        note("server: 6 requests under an 8 MiB budget")
+        ts = [to_dev(a) for a in reqs]
+        tks = [srv.submit(t) for t in ts]
+        for tk in tks:
+            assert srv.wait(tk, 60.0) == 0
+        infos = [srv.result(tk) for tk in tks]
+        for a, t, info in zip(reqs, ts, infos):
+            want, wp = oracle.sorted_copy(a)
+            assert_bit_equal(to_host(t), want, "budget-limited request")
+            assert info["first_pivot"] == wp
+        admits = [i["t_admit_s"] for i in infos]
+        assert admits == sorted(admits), "admission is FIFO"
+        st = srv.stats()
+        assert st["rejected"] == 1 and st["completed"] == 6 and st["budget_used_bytes"] == 0
+
+
+def test_cancel_queued():
+    from paper_1107_3622_amd import ksort
+    torch_dev()
+    with ksort.Server(8 * MIB, 1) as srv:
+        a = request_keys(300, 200_000, True)
+        b = request_keys(301, 200_000, True)
+        ta, tb = to_dev(a), to_dev(b)
+        note("server: cancel a queued request")
+        ka = srv.submit(ta)
+        kb = srv.submit(tb)
+        rc = srv.cancel(kb)
+        assert srv.wait(ka, 60.0) == 0
+        assert_bit_equal(to_host(ta), oracle.sorted_copy(a)[0], "request before the cancelled one")
+        if rc == 0:
+            assert srv.wait(kb, 60.0) == KSORT_ECANCELLED
+            assert srv.poll(kb) == KSORT_ECANCELLED
+            assert_bit_equal(to_host(tb), b, "a cancelled request is left untouched")
+        else:  # already admitted: it runs to completion
+            assert rc == KSORT_EAGAIN
+            assert srv.wait(kb, 60.0) == 0
+            assert_bit_equal(to_host(tb), oracle.sorted_copy(b)[0], "admitted request")
+        with pytest.raises(ksort.KsortError):
+            srv.poll(123456789)
+
+
+def test_poisson_stream_overlaps():
+    """A seeded Poisson stream: requests arrive while others are on the
+    device; every result equals torch.sort."""
+    from paper_1107_3622_amd import ksort
+    torch = torch_dev()
+    count = 120
+    sizes, is_f64, arrivals = synth.serve_requests(count, 12, 13, 11, 1_000, 100_000, 0.7, 2000.0)
+    reqs = [synth.torch_fill("uniform_f64" if f else "uniform_f32", synth.REQUEST_SEED_BASE + r, int(n), "cuda")
+            for r, (n, f) in enumerate(zip(sizes, is_f64))]
+    refs = [torch.sort(t)[0] for t in reqs]
+    torch.cuda.synchronize()
+    note(f"server: Poisson stream of {count} requests")
+    with ksort.Server(1 << 30, 32) as srv:
+        t0 = time.perf_counter()
+        tks = []
+        for t, at in zip(reqs, arrivals):
+            dt = at - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tks.append(srv.submit(t))
+        for tk in tks:
+            assert srv.wait(tk, 60.0) == 0
+        st = srv.stats()
+        infos = [srv.result(tk) for tk in tks]
+    for r, (t, ref) in enumerate(zip(reqs, refs)):
+        assert torch.equal(t, ref), f"request {r}"
+    # continuous batching: some request was admitted before an earlier one finished
+    overlaps = sum(1 for k in range(1, count) if infos[k]["t_admit_s"] < infos[k - 1]["t_done_s"])
+    assert overlaps > 0
+    assert st["completed"] == count and st["p99_latency_s"] > 0
