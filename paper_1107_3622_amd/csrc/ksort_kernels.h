@@ -160,10 +160,23 @@ __device__ __forceinline__ void store_seg(KS_GLOBAL Seg* d, const Seg& s) {
   d->first_tile = s.first_tile;
 }
 
+// What a stage holds, as every workgroup reads it at the start: partition
+// tiles, work tickets (finish tasks run in this stage, then tiles) and the
+// number of finish tasks carried over from the stage before.  Carried tasks
+// (upper half of the finish list) take the first tickets, so a task is
+// carried at most as long as newer ones keep the grid busy.
+struct Counts {
+  int32_t ntiles, nwork, ncar;
+};
+
+// Slot in the finish list of this stage's finish task number t.
+__device__ __forceinline__ int32_t fin_slot(const StageArgs& a, const Counts& cn, int32_t t) {
+  return t < cn.ncar ? a.fin_half + t : t - cn.ncar;
+}
+
 // Claims the next ticket of the stage and resolves it to a work item
 // (executed by one thread; the result goes to LDS for the block).
-__device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, int32_t ntiles, int32_t nwork,
-                                           Task* out) {
+__device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out) {
   const int par = a.stage & 1;
   const int32_t t = add_agent(&cur->ticket, 1);
   out->t = t;
@@ -171,11 +184,11 @@ __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, in
   // longer than a tile, so starting them first keeps them off the end of the
   // stage.  Partition tiles follow in segment order (the look-back relies on
   // a tile's predecessors holding lower tickets).
-  const int32_t nfin = nwork - ntiles;
+  const int32_t nfin = cn.nwork - cn.ntiles;
   if (t < nfin) {
-    load_seg(&out->seg, (const KS_GLOBAL Seg*)a.fin[par] + t);
+    load_seg(&out->seg, (const KS_GLOBAL Seg*)a.fin[par] + fin_slot(a, cn, t));
     out->kind = kTaskFinish;
-  } else if (t < nwork) {
+  } else if (t < cn.nwork) {
     const int32_t tt = t - nfin;
     const int32_t slot = ((const KS_GLOBAL int32_t*)a.tilemap[par])[tt];
     load_seg(&out->seg, (const KS_GLOBAL Seg*)a.live[par] + slot);
@@ -190,10 +203,9 @@ __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, in
 // but only while finish tickets remain: a partition tile is claimed only when
 // the block is free to load it, because every later tile of its segment waits
 // for its count in the look-back.
-__device__ __forceinline__ void claim_early(const StageArgs& a, StageCtr* cur, int32_t ntiles, int32_t nwork,
-                                            Task* out) {
-  if (ld_agent(&cur->ticket) < nwork - ntiles)
-    fetch_task(a, cur, ntiles, nwork, out);
+__device__ __forceinline__ void claim_early(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out) {
+  if (ld_agent(&cur->ticket) < cn.nwork - cn.ntiles)
+    fetch_task(a, cur, cn, out);
   else
     out->kind = kTaskUnclaimed;
 }
@@ -358,7 +370,7 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
           // a one-key side written into the caller's array is already final
         } else if (cn[c] >= 1) {
           const int32_t f = add_agent(&nx->nfin, 1);
-          if (f >= a.cap_fin) {
+          if (f >= a.fin_half) {
             st_agent(&a.flags->overflow, 1);
             continue;
           }
@@ -395,7 +407,7 @@ __device__ void emit_children(const StageArgs& a, int32_t* em_slot, int32_t* em_
 
 template <typename T, int BLOCK, int ITEMS>
 __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, BLOCK, ITEMS>& sm, StageCtr* cur,
-                               int32_t ntiles, int32_t nwork, Task* next) {
+                               const Counts& cn, Task* next) {
   constexpr int NW = BLOCK / kWave;
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int NC = ITEMS * NW;                 // per-(item, wave) counts
@@ -533,7 +545,7 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
   // a5/a6: the segment's last tile places the key and emits the two sides.
   if (o + cnt == len) emit_children<T, TILE>(a, sm.em_slot, sm.em_first, sm.em_nt, tk, xlt + tot_lt, key);
   // the block is free: claim its next work item
-  if (tid == BLOCK - 1) fetch_task(a, cur, ntiles, nwork, next);
+  if (tid == BLOCK - 1) fetch_task(a, cur, cn, next);
 }
 
 // ---------------------------------------------------------------------------
@@ -611,7 +623,7 @@ __device__ __forceinline__ uint32_t q_entry(int s, int L, int p) {
 
 template <typename T, int BLOCK, int CUT>
 __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, BLOCK, CUT>& sm, StageCtr* cur,
-                               int32_t ntiles, int32_t nwork, Task* next) {
+                               const Counts& cn, Task* next) {
   constexpr int NW = BLOCK / kWave;
   static_assert(CUT <= 4095, "queue entries hold 12-bit positions and lengths");
   const int tid = threadIdx.x, lane = lane_id();
@@ -631,7 +643,7 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
   if (len <= kSmall) {
     // one wave finishes the whole segment in registers
     if (tid < kWave) wave_rank_sort<T>((const KS_GLOBAL T*)src, dst, len, pivot_slot, pivot_bias);
-    if (tid == BLOCK - 1) claim_early(a, cur, ntiles, nwork, next);
+    if (tid == BLOCK - 1) claim_early(a, cur, cn, next);
   } else {
     {
       // all loads in flight before the first LDS store
@@ -652,7 +664,7 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
       sm.outstanding = 1;
     }
     __syncthreads();
-    if (tid == BLOCK - 1) claim_early(a, cur, ntiles, nwork, next);
+    if (tid == BLOCK - 1) claim_early(a, cur, cn, next);
     // Each wave takes sub-segments from the queue until none is outstanding;
     // after a partition it keeps the smaller side for itself and queues the
     // other.  Every branch of this loop is taken on a wave-uniform value
@@ -718,7 +730,7 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
     const int32_t old = add_agent(a.pending + tk.buf, -1);
     if (old - 1 == 0 && a.done_stage) st_agent(a.done_stage + tk.buf, a.stage);
   }
-  if (tid == BLOCK - 1 && next->kind == kTaskUnclaimed) fetch_task(a, cur, ntiles, nwork, next);
+  if (tid == BLOCK - 1 && next->kind == kTaskUnclaimed) fetch_task(a, cur, cn, next);
 }
 
 // ---------------------------------------------------------------------------
@@ -728,8 +740,9 @@ template <typename T, int BLOCK, int ITEMS, int CUT>
 __global__ __launch_bounds__(BLOCK) void stage_kernel(StageArgs a) {
   __shared__ StageSmem<T, BLOCK, ITEMS, CUT> sm;
   __shared__ Task next;
-  __shared__ int32_t s_counts[2];
+  __shared__ int32_t s_counts[4];
   StageCtr* cur = a.ctr + (a.stage % 3);
+  StageCtr* nx = a.ctr + ((a.stage + 1) % 3);
   if (threadIdx.x == BLOCK - 1) {
     if (blockIdx.x == 0) {
       StageCtr* nn = a.ctr + ((a.stage + 2) % 3);
@@ -737,30 +750,58 @@ __global__ __launch_bounds__(BLOCK) void stage_kernel(StageArgs a) {
       st_agent(&nn->ntiles, 0);
       st_agent(&nn->nfin, 0);
       st_agent(&nn->ticket, 0);
+      st_agent(&nn->carry, 0);
     }
     // after a failed consistency check the lists may be incomplete: do
     // nothing (the host reports the error)
     const int32_t ovf = ld_agent(&a.flags->overflow);
     const int32_t nt = min(ld_agent(&cur->ntiles), a.cap_tiles);
-    const int32_t nf = min(ld_agent(&cur->nfin), a.cap_fin);
+    const int32_t ncar = min(ld_agent(&cur->carry), a.cap_fin - a.fin_half);
+    const int32_t nf = ncar + min(ld_agent(&cur->nfin), a.fin_half);
+    // A stage that also partitions runs at most fin_run finish tasks, one
+    // round on the grid; the rest wait for the next stage, whose partitions
+    // are fewer, instead of a second round that would end this stage late.
+    const int32_t ndef = nt > 0 && nf > a.fin_run ? min(nf - a.fin_run, a.cap_fin - a.fin_half) : 0;
+    const Counts cn{nt, nt + nf - ndef, ncar};
     if (ovf != 0)
       next.kind = kTaskNone;
     else
-      fetch_task(a, cur, nt, nt + nf, &next);
-    s_counts[0] = nt;
-    s_counts[1] = nt + nf;
+      fetch_task(a, cur, cn, &next);
+    s_counts[0] = cn.ntiles;
+    s_counts[1] = cn.nwork;
+    s_counts[2] = cn.ncar;
+    s_counts[3] = ovf != 0 ? 0 : ndef;
   }
   __syncthreads();
-  const int32_t ntiles = uniform(s_counts[0]);
-  const int32_t nwork = uniform(s_counts[1]);
+  const Counts cn{uniform(s_counts[0]), uniform(s_counts[1]), uniform(s_counts[2])};
+  const int32_t ndef = uniform(s_counts[3]);
+  if (ndef > 0) {
+    // carry the deferred finish tasks (the last ndef finish tickets) into
+    // the upper half of the next stage's finish list
+    const int par = a.stage & 1;
+    const int32_t nrun = cn.nwork - cn.ntiles;
+    for (int32_t j = blockIdx.x * BLOCK + threadIdx.x; j < ndef; j += gridDim.x * BLOCK) {
+      Seg d;
+      load_seg(&d, (const KS_GLOBAL Seg*)a.fin[par] + fin_slot(a, cn, nrun + j));
+      store_seg((KS_GLOBAL Seg*)a.fin[par ^ 1] + a.fin_half + j, d);
+      if (a.stage_keys && a.stage + 1 < a.cap_stats) {
+        atomicAdd((unsigned long long*)&a.stage_keys[2 * (a.stage + 1) + 1], (unsigned long long)d.len);
+        atomicAdd((unsigned long long*)&a.stage_keys[2 * a.stage + 1], (unsigned long long)(-d.len));
+      }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st_agent(&nx->carry, ndef);
+      atomicMax(&a.flags->last_active, a.stage + 1);
+    }
+  }
   for (;;) {
     const TaskU tk = read_task(&next);
     __syncthreads();  // everyone has read `next` before it is overwritten
     if (tk.kind == kTaskNone) break;
     if (tk.kind == kTaskTile)
-      partition_tile<T, BLOCK, ITEMS>(a, tk, sm.p, cur, ntiles, nwork, &next);
+      partition_tile<T, BLOCK, ITEMS>(a, tk, sm.p, cur, cn, &next);
     else
-      finish_segment<T, BLOCK, CUT>(a, tk, sm.f, cur, ntiles, nwork, &next);
+      finish_segment<T, BLOCK, CUT>(a, tk, sm.f, cur, cn, &next);
     __syncthreads();
   }
 }
@@ -782,6 +823,7 @@ __global__ void reset_kernel(StageCtr* ctr, Flags* flags, int64_t* stage_keys, i
     ctr[tid].ntiles = 0;
     ctr[tid].nfin = 0;
     ctr[tid].ticket = 0;
+    ctr[tid].carry = 0;
   }
   if (tid == 0) {
     flags->last_active = -1;
@@ -839,7 +881,7 @@ __global__ void init_kernel(InitArgs ia) {
       if (a.pivot_out) a.pivot_out[root] = -1;
     } else if (!ia.level_mode && len <= a.cutoff) {
       const int32_t f = add_agent(&c0->nfin, 1);
-      if (f < a.cap_fin) {
+      if (f < a.fin_half) {
         a.fin[par][f] = d;
         ++nseg;
         if (a.stage_keys && a.stage < a.cap_stats)

@@ -170,7 +170,7 @@ static size_t arena_bytes_for(const Caps& c, int cap_stats) {
   b += align256(sizeof(Flags));
   b += 2 * align256((size_t)c.live * sizeof(Seg));
   b += 2 * align256((size_t)c.tiles * sizeof(int32_t));
-  b += 2 * align256((size_t)c.fin * sizeof(Seg));
+  b += 2 * align256((size_t)2 * c.fin * sizeof(Seg));  // children below caps.fin, carried tasks above
   b += align256((size_t)c.tiles * sizeof(uint64_t));
   b += align256((size_t)cap_stats * 2 * sizeof(int64_t));
   b += 2 * align256((size_t)c.bufs * sizeof(int32_t));
@@ -213,7 +213,7 @@ int Workspace::reserve(const Caps& c, size_t scratch_need) {
     flags = (Flags*)take(sizeof(Flags));
     for (int k = 0; k < 2; ++k) live[k] = (Seg*)take((size_t)nc.live * sizeof(Seg));
     for (int k = 0; k < 2; ++k) tilemap[k] = (int32_t*)take((size_t)nc.tiles * sizeof(int32_t));
-    for (int k = 0; k < 2; ++k) fin[k] = (Seg*)take((size_t)nc.fin * sizeof(Seg));
+    for (int k = 0; k < 2; ++k) fin[k] = (Seg*)take((size_t)2 * nc.fin * sizeof(Seg));
     status = (uint64_t*)take((size_t)nc.tiles * sizeof(uint64_t));
     stage_keys = (int64_t*)take((size_t)cap_stats * 2 * sizeof(int64_t));
     pending = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
@@ -257,6 +257,10 @@ void release_workspaces() {
 
 // ---------------------------------------------------------------- launches
 
+#ifndef KSORT_FIN_RUN
+#define KSORT_FIN_RUN(grid) (grid)
+#endif
+
 constexpr uint32_t kEpochSpan = (1u << 22) - 1;  // epochs 1 .. 2^22-1
 
 static uint32_t epoch_of(int stage) { return (uint32_t)(stage % kEpochSpan) + 1; }
@@ -279,7 +283,11 @@ StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_
   a.stage_keys = ws.stage_keys;
   a.cap_live = (int32_t)ws.caps.live;
   a.cap_tiles = (int32_t)ws.caps.tiles;
-  a.cap_fin = (int32_t)ws.caps.fin;
+  // A stage's finish list holds the children of the stage before below
+  // caps.fin and the finish tasks carried over from it above.
+  a.fin_half = (int32_t)ws.caps.fin;
+  a.cap_fin = (int32_t)(2 * ws.caps.fin);
+  a.fin_run = 0x7fffffff;
   a.cap_stats = ws.cap_stats;
   a.stage = stage;
   a.epoch = epoch_of(stage);
@@ -318,6 +326,8 @@ int stage_grid(const Variant& v, const DeviceInfo& di, const Caps& c) {
 
 int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid) {
   StageArgs args = a;
+  // one round of finish tasks on the grid in a stage that also partitions
+  args.fin_run = KSORT_FIN_RUN(grid);
   void* params[] = {&args};
   KSORT_HIP(hipLaunchKernel(v.stage, dim3(grid), dim3(v.block), params, 0, ws.stream));
   return KSORT_OK;

@@ -33,7 +33,8 @@ struct StageCtr {
   int32_t ntiles;    // partition tickets reserved
   int32_t nfin;      // finish segments appended
   int32_t ticket;    // work tickets claimed
-  int32_t pad[4];
+  int32_t carry;     // finish tasks carried over from the stage before (upper half of the list)
+  int32_t pad[3];
 };
 
 struct Flags {
@@ -60,6 +61,8 @@ struct StageArgs {
   int32_t cutoff;         // sides of at most this many keys go to finish work
   int32_t emit_children;  // 0: one level only (no recursion)
   int32_t pivot_relative; // pivot reported as i - left (1) or as i (0)
+  int32_t fin_run;        // finish tasks a stage with partition tiles runs; the rest wait a stage
+  int32_t fin_half;       // finish lists: children below this index, carried tasks from it up
 };
 
 // Arguments of the set-up kernel that turns input arrays (or, for a single
