@@ -96,6 +96,26 @@ StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_
                      int emit_children);
 
 // Launch helpers (asynchronous on ws.stream).
+// Stage kernels of this library never run concurrently on one device (their
+// first work items are fixed per workgroup; see the stage kernel): each
+// batch of stage launches waits for the previous batch on the device,
+// whatever stream it was enqueued on.  Hold an OrderedLaunches while
+// enqueuing a batch; its destructor marks the batch's end.
+class OrderedLaunches {
+ public:
+  OrderedLaunches(int device, hipStream_t stream);
+  ~OrderedLaunches();
+  OrderedLaunches(const OrderedLaunches&) = delete;
+  OrderedLaunches& operator=(const OrderedLaunches&) = delete;
+  int status() const { return rc_; }
+  struct Order;
+
+ private:
+  Order* o_;
+  hipStream_t stream_;
+  int rc_ = 0;
+};
+
 int launch_reset(Workspace& ws);
 int launch_init(Workspace& ws, const Variant& v, const InitArgs& ia, int64_t nblocks);
 int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid);

@@ -176,9 +176,19 @@ __device__ __forceinline__ int32_t fin_slot(const StageArgs& a, const Counts& cn
 
 // Claims the next ticket of the stage and resolves it to a work item
 // (executed by one thread; the result goes to LDS for the block).
-__device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out) {
+//
+// Workgroup b takes ticket b as its first work item without an atomic (512
+// simultaneous claims on one counter would cost several microseconds per
+// stage); later tickets come from the stage's counter, offset by the grid
+// size.  A partition tile waits in its look-back for tiles with lower
+// tickets, so every ticket must belong to a workgroup that runs: the grid
+// never exceeds what the device holds at once, and the host orders all
+// stage-kernel launches of a device one after another, so no other kernel
+// that waits on its own workgroups can keep some of ours from starting.
+__device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out,
+                                           int32_t first = -1) {
   const int par = a.stage & 1;
-  const int32_t t = add_agent(&cur->ticket, 1);
+  const int32_t t = first >= 0 ? first : add_agent(&cur->ticket, 1) + (int32_t)gridDim.x;
   out->t = t;
   // Finish tasks take the first tickets: they never wait on anyone and take
   // longer than a tile, so starting them first keeps them off the end of the
@@ -204,7 +214,7 @@ __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, co
 // the block is free to load it, because every later tile of its segment waits
 // for its count in the look-back.
 __device__ __forceinline__ void claim_early(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out) {
-  if (ld_agent(&cur->ticket) < cn.nwork - cn.ntiles)
+  if (ld_agent(&cur->ticket) + (int32_t)gridDim.x < cn.nwork - cn.ntiles)
     fetch_task(a, cur, cn, out);
   else
     out->kind = kTaskUnclaimed;
@@ -766,7 +776,7 @@ __global__ __launch_bounds__(BLOCK) void stage_kernel(StageArgs a) {
     if (ovf != 0)
       next.kind = kTaskNone;
     else
-      fetch_task(a, cur, cn, &next);
+      fetch_task(a, cur, cn, &next, (int32_t)blockIdx.x);
     s_counts[0] = cn.ntiles;
     s_counts[1] = cn.nwork;
     s_counts[2] = cn.ncar;

@@ -297,6 +297,37 @@ StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_
   return a;
 }
 
+// ---------------------------------------------------------------- launch order
+
+struct OrderedLaunches::Order {
+  std::mutex mu;
+  hipEvent_t last = nullptr;  // end of the latest batch of stage launches on the device
+};
+
+static std::mutex g_order_mu;
+static std::map<int, std::unique_ptr<OrderedLaunches::Order>> g_order;
+
+OrderedLaunches::OrderedLaunches(int device, hipStream_t stream) : stream_(stream) {
+  {
+    std::lock_guard<std::mutex> lk(g_order_mu);
+    auto& p = g_order[device];
+    if (!p) p.reset(new Order);
+    o_ = p.get();
+  }
+  o_->mu.lock();
+  hipError_t e = hipSuccess;
+  if (!o_->last)
+    e = hipEventCreateWithFlags(&o_->last, hipEventDisableTiming);
+  else
+    e = hipStreamWaitEvent(stream, o_->last, 0);
+  if (e != hipSuccess) rc_ = hip_fail(e, "ordering stage launches");
+}
+
+OrderedLaunches::~OrderedLaunches() {
+  if (o_->last) (void)hipEventRecord(o_->last, stream_);
+  o_->mu.unlock();
+}
+
 int launch_reset(Workspace& ws) {
   const int64_t nwords = ws.caps.tiles;
   const int blocks = (int)std::min<int64_t>(1024, (nwords + 255) / 256);
@@ -483,7 +514,11 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       ge.scratch = ws.scratch;
       it = g_graphs.emplace(gk, ge).first;
     }
-    KSORT_HIP(hipGraphLaunch(it->second.exec, stream));
+    {
+      OrderedLaunches order(dev, stream);
+      if (order.status()) return order.status();
+      KSORT_HIP(hipGraphLaunch(it->second.exec, stream));
+    }
     KSORT_HIP(hipStreamSynchronize(stream));
     stage = it->second.stages;
     graphed = true;
@@ -498,6 +533,9 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
     if (graphed) {
       graphed = false;  // flags were read back by the graph
     } else {
+     {
+      OrderedLaunches order(dev, stream);
+      if (order.status()) return order.status();
       for (int b = 0; b < batch; ++b, ++stage) {
         if (stage > 0 && stage % (int)kEpochSpan == 0) {
           const int64_t nwords = ws.caps.tiles;
@@ -521,6 +559,7 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
         if (rc) return rc;
       }
       KSORT_HIP(hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, stream));
+     }
       KSORT_HIP(hipStreamSynchronize(stream));
     }
     const Flags f = *ws.h_flags;
@@ -597,7 +636,11 @@ static int run_level(int dtype, const void* d_in, void* d_out, int64_t n, const 
   rc = launch_init(ws, *v, ia, nseg);
   if (rc) return rc;
   const int grid = stage_grid(*v, *di, ws.caps);
-  rc = launch_stage(ws, *v, stage_args(ws, *v, 0, d_pivot, 0, 0), grid);
+  {
+    OrderedLaunches order(dev, stream);
+    if (order.status()) return order.status();
+    rc = launch_stage(ws, *v, stage_args(ws, *v, 0, d_pivot, 0, 0), grid);
+  }
   if (rc) return rc;
   KSORT_HIP(hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, stream));
   KSORT_HIP(hipStreamSynchronize(stream));

@@ -158,8 +158,12 @@ static int lane_launch(ksort_server* s, Lane& L) {
     int rc = launch_reset(L.ws);  // look-back tags wrap: clear them
     if (rc) return rc;
   }
-  int rc = launch_stage(L.ws, *L.v, server_args(L), L.grid);
-  if (rc) return rc;
+  {
+    OrderedLaunches order(s->device, L.stream);
+    if (order.status()) return order.status();
+    int rc = launch_stage(L.ws, *L.v, server_args(L), L.grid);
+    if (rc) return rc;
+  }
   const size_t slots = (size_t)s->max_inflight;
   KSORT_HIP(hipMemcpyAsync(L.h_done, L.ws.done_stage, slots * sizeof(int32_t), hipMemcpyDeviceToHost, L.stream));
   KSORT_HIP(hipMemcpyAsync(L.h_pivot, L.d_pivot, slots * sizeof(int64_t), hipMemcpyDeviceToHost, L.stream));
