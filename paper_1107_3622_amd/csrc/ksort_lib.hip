@@ -61,13 +61,13 @@ static Variant make_variant(int dtype) {
 
 const std::vector<Variant>& variants() {
   static const std::vector<Variant> vs = {
+      make_variant<double, 512, 24, 2048>(KSORT_F64),
       make_variant<double, 512, 16, 2048>(KSORT_F64),
       make_variant<double, 1024, 8, 2048>(KSORT_F64),
-      make_variant<double, 256, 32, 2048>(KSORT_F64),
       make_variant<double, 512, 16, 1024>(KSORT_F64),
+      make_variant<float, 512, 24, 2048>(KSORT_F32),
       make_variant<float, 512, 16, 2048>(KSORT_F32),
       make_variant<float, 1024, 8, 2048>(KSORT_F32),
-      make_variant<float, 256, 32, 2048>(KSORT_F32),
       make_variant<float, 512, 16, 1024>(KSORT_F32),
   };
   return vs;
@@ -98,7 +98,7 @@ const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n) {
   }
   std::lock_guard<std::mutex> lk(g_default_mu);
   int j = g_default[dtype];
-  if (j < 0) j = variant_index(dtype, 512, 16, 2048);
+  if (j < 0) j = variant_index(dtype, 512, 24, 2048);
   return &vs[j];
 }
 

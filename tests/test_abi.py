@@ -49,10 +49,10 @@ def test_host_only_calls(lib):
     from paper_1107_3622_amd import ksort
     v64 = ksort.ksort_variants(ksort.KSORT_F64)
     v32 = ksort.ksort_variants(ksort.KSORT_F32)
-    for v in [(512, 16, 2048), (1024, 8, 2048), (256, 32, 2048), (512, 16, 1024)]:
+    for v in [(512, 24, 2048), (512, 16, 2048), (1024, 8, 2048), (512, 16, 1024)]:
         assert v in v64 and v in v32
-    assert ksort.ksort_get_default(ksort.KSORT_F64) == (512, 16, 2048)
-    assert ksort.ksort_get_default(ksort.KSORT_F32) == (512, 16, 2048)
+    assert ksort.ksort_get_default(ksort.KSORT_F64) == (512, 24, 2048)
+    assert ksort.ksort_get_default(ksort.KSORT_F32) == (512, 24, 2048)
     assert lib.ksort_variants(7, None, 0) == -1
     # workspace: scratch of n keys plus descriptors, grows with n
     b1 = ksort.ksort_workspace_bytes(ksort.KSORT_F64, 1_000_000)
@@ -68,7 +68,7 @@ def test_set_default_rejects_unknown_variant(lib):
     ksort.ksort_set_default(ksort.KSORT_F64, (1024, 8, 2048))
     assert ksort.ksort_get_default(ksort.KSORT_F64) == (1024, 8, 2048)
     ksort.ksort_set_default(ksort.KSORT_F64, None)
-    assert ksort.ksort_get_default(ksort.KSORT_F64) == (512, 16, 2048)
+    assert ksort.ksort_get_default(ksort.KSORT_F64) == (512, 24, 2048)
 
 
 def test_product_path_has_no_cpu_fallback():
