@@ -16,6 +16,10 @@ Prints ONE JSON line:
                         sort of the same key count
   serve                 a seeded Poisson stream of requests through the sort
                         server: p50/p99 latency and keys/s
+  statbound             the paper's run-time model (Section 3) fitted to
+                        this sort over Table 1's sizes
+  worst_case            sorted, reversed, all-equal and four-valued inputs:
+                        level passes and time
   cpu_baseline          the literal CPU oracle on the host, one thread
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
@@ -54,6 +58,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     p.add_argument("--no-extras", action="store_true", help="skip the batched and serving legs")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--readings", type=int, default=50, help="sorts per size in the statistical-bound leg")
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only run device copies of this many bytes (counter calibration)")
     return p.parse_args()
@@ -199,6 +204,69 @@ def serve_leg(ksort, torch) -> dict:
             "completed": st["completed"], "failed": st["failed"], "verified": bool(ok)}
 
 
+TABLE1_N = [100_000, 500_000, 1_000_000, 2_500_000, 5_000_000, 6_000_000, 7_000_000, 7_100_000, 7_500_000,
+            10_000_000]
+
+
+def statbound_leg(ksort, torch, readings: int) -> dict:
+    """The paper's statistical-bound model (Section 3) fitted to this sort:
+    mean time of `readings` sorts of fresh U[0,1) FP64 arrays at each size of
+    Table 1, then the OLS fit of y = b0 + b1 n log2 n + b2 n."""
+    import synth
+    from paper_1107_3622_amd import statbound
+    means = []
+    for i, n in enumerate(TABLE1_N):
+        src = synth.torch_fill("uniform_f64", 100 + i, n, "cuda")
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(readings)]
+        t = src.clone()
+        ksort.ksort_f64(t)  # warm
+        for r in range(readings):
+            t.copy_(src)
+            ev[r][0].record()
+            ksort.ksort_f64(t)
+            ev[r][1].record()
+        torch.cuda.synchronize()
+        means.append(sum(a.elapsed_time(b) for a, b in ev) / readings / 1e3)
+        del src, t
+    fr = statbound.ols(TABLE1_N, means)
+    log("statistical bound of the GPU sort (seconds):\n" + statbound.report(fr, "y(GPU)"))
+    return {"n": TABLE1_N, "mean_s": means, "readings": readings,
+            "coef": [float(c) for c in fr.coef], "se": [float(x) for x in fr.se], "t": [float(x) for x in fr.t],
+            "p": [float(x) for x in fr.p], "r2": fr.r2, "r2_adj": fr.r2_adj, "r2_pred": fr.r2_pred, "s": fr.s,
+            "f": fr.f, "seq_ss": [float(x) for x in fr.seq_ss], "large_residuals": fr.large}
+
+
+def worstcase_leg(ksort, torch, n: int = 16_384) -> dict:
+    """K-sort's worst cases at n keys: ordered inputs and heavy duplicates
+    make each partition peel off one key, so the level passes grow to about
+    n and the work to about n^2 / 2 key moves (no change to the key rule)."""
+    import numpy as np
+
+    import synth
+    u = synth.uniform_f64(901, n)
+    kinds = {"random": u, "sorted": np.sort(u), "reversed": np.sort(u)[::-1].copy(),
+             "all_equal": np.full(n, 0.5), "four_values": np.floor(synth.uniform_f64(902, n) * 4.0) / 4.0}
+    out = {}
+    for name, a in kinds.items():
+        src = torch.from_numpy(a).to("cuda")
+        t = src.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ksort.ksort_f64(t)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t2 = src.clone()
+        ksort.ksort_profile_read()
+        ksort.ksort_profile_enable(True)
+        ksort.ksort_f64(t2)
+        ksort.ksort_profile_enable(False)
+        recs = ksort.ksort_profile_read()
+        levels = sum(1 for r in recs if r["live_keys"] + r["finish_keys"] > 0)
+        ok = bool(torch.equal(t, torch.sort(src)[0]))
+        out[name] = {"ms": dt * 1e3, "levels": levels, "launches": len(recs), "verified": ok}
+    return {"n": n, "inputs": out}
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
@@ -309,6 +377,11 @@ def main() -> int:
         out["batched"] = batched_leg(ksort, torch)
         log("serving leg")
         out["serve"] = serve_leg(ksort, torch)
+        log("statistical-bound leg")
+        out["statbound"] = statbound_leg(ksort, torch, args.readings)
+        log("worst-case leg")
+        out["worst_case"] = worstcase_leg(ksort, torch)
+        ok = ok and all(v["verified"] for v in out["worst_case"]["inputs"].values())
         ok = ok and out["batched"]["verified"] and out["serve"]["verified"]
     if not args.no_cpu:
         log("timing the CPU oracle")

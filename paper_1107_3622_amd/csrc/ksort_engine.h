@@ -53,6 +53,7 @@ int device_info(int ordinal, const DeviceInfo** out);
 // Capacities of the descriptor lists for one run.
 struct Caps {
   int64_t live = 0, tiles = 0, fin = 0, bufs = 1;
+  int64_t stats = 256;  // level passes whose key counts are kept for profiling
 };
 Caps caps_for(const Variant& v, int64_t n, int64_t nseg, bool level_mode);
 

@@ -158,6 +158,8 @@ Caps caps_for(const Variant& v, int64_t n, int64_t nseg, bool level_mode) {
     // stage 0 may hold every small input array; later stages at most two
     // sides per live segment of the stage before
     c.fin = std::max<int64_t>(nseg, 2 * c.live) + 2;
+    // a sort of n keys takes at most about n level passes (ordered inputs)
+    c.stats = std::min<int64_t>(n, 65536) + 64;
   }
   return c;
 }
@@ -187,13 +189,16 @@ Workspace::~Workspace() {
 
 int Workspace::reserve(const Caps& c, size_t scratch_need) {
   if (!h_flags) KSORT_HIP(hipHostMalloc((void**)&h_flags, sizeof(Flags), hipHostMallocDefault));
-  const bool fits = c.live <= caps.live && c.tiles <= caps.tiles && c.fin <= caps.fin && c.bufs <= caps.bufs;
+  const bool fits = c.live <= caps.live && c.tiles <= caps.tiles && c.fin <= caps.fin && c.bufs <= caps.bufs &&
+                    c.stats <= caps.stats;
   if (!arena || !fits) {
     Caps nc;
     nc.live = std::max(c.live, caps.live);
     nc.tiles = std::max(c.tiles, caps.tiles);
     nc.fin = std::max(c.fin, caps.fin);
     nc.bufs = std::max(c.bufs, caps.bufs);
+    nc.stats = std::max(c.stats, caps.stats);
+    cap_stats = (int)nc.stats;
     if (arena) {
       KSORT_HIP(hipStreamSynchronize(stream));
       KSORT_HIP(hipFree(arena));
