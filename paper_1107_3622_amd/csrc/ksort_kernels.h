@@ -263,6 +263,8 @@ struct FinSmem {
   T buf[2][CUT];       // ping-pong buffers of the segment
   uint32_t q[QCAP];    // sub-segment queue; 0 = slot not yet written
   int32_t q_head, q_tail, outstanding;
+  int32_t bcnt[(CUT / BLOCK) * NW];  // workgroup partition: per-(item, wave) counts
+  int32_t bc;                        // workgroup partition: smaller keys in the sub-segment
 };
 
 template <typename T, int BLOCK, int ITEMS, int CUT>
@@ -562,6 +564,7 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
 // finish work
 
 constexpr int kSmall = kWave;  // sub-segments of at most this many keys finish in registers
+constexpr int kBlockSide = 256;  // sides longer than this get a workgroup partition at the top
 
 // Sorts in[0 .. L-1] (1 <= L <= 64) into out[0 .. L-1] with one wave, one key
 // per lane, by placing every key at its rank: the number of keys smaller than
@@ -627,6 +630,57 @@ __device__ int wave_partition(const T* in, T* out, int s, int L, T key) {
   return cl;
 }
 
+// Steps 1-4 on sm.buf[p][s .. s+L-1] by the whole workgroup, into
+// sm.buf[p^1][s .. s+L-1]: the keys smaller than the first (the segment's
+// key) fill [s, s+c) in position order, the key goes to s+c, where it is
+// final (also written to dst), and the others fill (s+c, s+L) in position
+// order.  Returns c.  s, L and p are the same in every thread; L <= CUT.
+template <typename T, int BLOCK, int CUT>
+__device__ int block_partition(FinSmem<T, BLOCK, CUT>& sm, int p, int s, int L, T* dst) {
+  constexpr int NW = BLOCK / kWave;
+  constexpr int PER = CUT / BLOCK;
+  static_assert(CUT % BLOCK == 0 && PER * NW <= kWave, "one wave scans the per-(item, wave) counts");
+  const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+  const T key = sm.buf[p][s];
+  T x[PER];
+  uint64_t bl[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = u * BLOCK + tid;
+    x[u] = q < L ? sm.buf[p][s + q] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = u * BLOCK + tid;
+    bl[u] = __ballot(q > 0 && q < L && !(key <= x[u]));
+    if (lane == 0) sm.bcnt[u * NW + w] = __popcll(bl[u]);
+  }
+  __syncthreads();
+  if (w == 0) {
+    const int c = lane < PER * NW ? sm.bcnt[lane] : 0;
+    const int inc = wave_inclusive_scan(c);
+    if (lane < PER * NW) sm.bcnt[lane] = inc - c;
+    if (lane == kWave - 1) sm.bc = inc;
+  }
+  __syncthreads();
+  const int c = uniform(sm.bc);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int q = u * BLOCK + tid;
+    if (q > 0 && q < L) {
+      const int r = sm.bcnt[u * NW + w] + mbcnt(bl[u]);  // smaller keys before q
+      const int d = ((bl[u] >> lane) & 1) ? r : c + 1 + (q - 1 - r);
+      sm.buf[p ^ 1][s + d] = x[u];
+    }
+  }
+  if (tid == 0) {
+    sm.buf[p ^ 1][s + c] = key;
+    gst<T>(dst, (uint32_t)((s + c) * sizeof(T)), key);
+  }
+  __syncthreads();
+  return c;
+}
+
 __device__ __forceinline__ uint32_t q_entry(int s, int L, int p) {
   return 1u | ((uint32_t)p << 1) | ((uint32_t)s << 2) | ((uint32_t)L << 14);
 }
@@ -666,15 +720,43 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
         if (tid < len - k * BLOCK) sm.buf[0][k * BLOCK + tid] = v[k];
     }
     for (int x = tid; x < len + NW + 2; x += BLOCK) sm.q[x] = 0;
-    __syncthreads();
     if (tid == 0) {
-      sm.q[0] = q_entry(0, len, 0);
-      sm.q_tail = 1;
+      sm.q_tail = 0;
       sm.q_head = 0;
-      sm.outstanding = 1;
+      sm.outstanding = 0;
     }
     __syncthreads();
     if (tid == BLOCK - 1) claim_early(a, cur, cn, next);
+    // The top of the recursion runs on the whole workgroup: the segment
+    // itself, then each of its sides of more than kBlockSide keys.  This cuts
+    // the chain of large partitions that a single wave would otherwise do
+    // alone while the others wait, and the queue starts with up to four
+    // sub-segments.  Sides of one key are final.
+    auto settle = [&](int s, int L, int p) {  // executed by thread 0
+      if (L == 1) {
+        gst<T>(dst, (uint32_t)(s * sizeof(T)), sm.buf[p][s]);
+      } else if (L >= 2) {
+        sm.q[sm.q_tail++] = q_entry(s, L, p);
+        ++sm.outstanding;
+      }
+    };
+    const int c1 = block_partition<T, BLOCK, CUT>(sm, 0, 0, len, dst);
+    if (tid == 0 && pivot_slot) *pivot_slot = pivot_bias + c1;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int s = side == 0 ? 0 : c1 + 1;
+      const int L = side == 0 ? c1 : len - 1 - c1;
+      if (L > kBlockSide) {
+        const int c2 = block_partition<T, BLOCK, CUT>(sm, 1, s, L, dst);
+        if (tid == 0) {
+          settle(s, c2, 0);
+          settle(s + c2 + 1, L - 1 - c2, 0);
+        }
+      } else if (tid == 0) {
+        settle(s, L, 1);
+      }
+    }
+    __syncthreads();
     // Each wave takes sub-segments from the queue until none is outstanding;
     // after a partition it keeps the smaller side for itself and queues the
     // other.  Every branch of this loop is taken on a wave-uniform value
@@ -706,10 +788,7 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
         const T key = sm.buf[p][s];
         const int cl = wave_partition<T>(sm.buf[p], sm.buf[p ^ 1], s, L, key);
         const int cg = L - 1 - cl;
-        if (lane == 0) {
-          gst<T>(dst, (uint32_t)((s + cl) * sizeof(T)), key);  // Step-4: the key is final
-          if (pivot_slot && L == len) *pivot_slot = pivot_bias + cl;
-        }
+        if (lane == 0) gst<T>(dst, (uint32_t)((s + cl) * sizeof(T)), key);  // Step-4: the key is final
         // Steps 5-6 on the two sides (a side of one key is final)
         if (cl == 1 && lane == 0) gst<T>(dst, (uint32_t)(s * sizeof(T)), sm.buf[p ^ 1][s]);
         if (cg == 1 && lane == 0) gst<T>(dst, (uint32_t)((s + cl + 1) * sizeof(T)), sm.buf[p ^ 1][s + cl + 1]);
