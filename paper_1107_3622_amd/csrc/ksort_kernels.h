@@ -101,6 +101,20 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
   return v;
 }
 
+// Sum of v over the 64 lanes of a wave, returned in every lane.  Row shifts
+// by 1, 2, 4 and 8 leave each 16-lane row's sum in its last lane; the row
+// broadcasts of lanes 15 and 31 then carry it across rows, so lane 63 holds
+// the total.  Every lane of the wave must be active.
+__device__ __forceinline__ int wave_sum(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1 and 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2 and 3
+  return __builtin_amdgcn_readlane(v, kWave - 1);
+}
+
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
@@ -265,6 +279,7 @@ struct FinSmem {
   int32_t q_head, q_tail, outstanding;
   int32_t bcnt[(CUT / BLOCK) * NW];  // workgroup partition: per-(item, wave) counts
   int32_t bc;                        // workgroup partition: smaller keys in the sub-segment
+  int32_t tie[NW][kWave];            // per wave: placement of equal keys in a leaf
 };
 
 template <typename T, int BLOCK, int ITEMS, int CUT>
@@ -596,10 +611,45 @@ __device__ void wave_rank_sort(const In* in, T* out, int L, int64_t* pivot_slot,
   if (pivot_slot && lane == 0) *pivot_slot = pivot_bias + rank;
 }
 
+// The same placement for a sub-segment held in LDS (2 <= L <= 64): every
+// lane reads the keys it compares with as LDS broadcasts, two per read, and
+// the main pass counts only the strictly smaller keys, one compare per pair.
+// Those counts are the ranks exactly when the keys are distinct, which holds
+// if and only if they sum to L(L-1)/2 (distinct ranks are 0 .. L-1, and a tie
+// gives its keys the lower rank).  Otherwise the keys of a tie share a count
+// c and must fill c, c+1, ...; they are equal bit for bit (total order), so
+// any assignment among them gives the same array, and an LDS atomic on a
+// per-wave counter for c hands them out.
+template <typename T>
+__device__ void lds_rank_sort(const T* in, T* out, int L, int32_t* tie) {
+  const int lane = lane_id();
+  const T v = lane < L ? in[lane] : T(0);
+  int rank = 0;
+  int j = 0;
+  for (; j + 8 <= L; j += 8) {
+    T b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = in[j + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rank += (int)(b[u] < v);
+  }
+  for (; j < L; ++j) rank += (int)(in[j] < v);
+  if (lane >= L) rank = 0;
+  if (wave_sum(rank) != L * (L - 1) / 2) {
+    tie[lane] = 0;
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the counters are clear before any increment
+    if (lane < L) rank += atomicAdd(&tie[rank], 1);
+  }
+  if (lane < L) gst<T>(out, (uint32_t)(rank * sizeof(T)), v);
+}
+
 // One partition of in[s .. s+L-1] into out[s .. s+L-1] by one wave (Steps
 // 1-4 on a sub-segment): smaller keys fill upward from s, the others downward
 // from s+L-1.  Returns the number of smaller keys.  Four 64-key chunks are
-// read before any is written, so one LDS round trip serves four chunks.
+// read before any is written, so one LDS round trip serves four chunks.  The
+// valid lanes of a chunk are a prefix of the wave, so a lane's place among
+// the other keys is its lane number minus its place among the smaller ones,
+// and each lane makes one write.
 template <typename T>
 __device__ int wave_partition(const T* in, T* out, int s, int L, T key) {
   constexpr int U = 4;
@@ -615,16 +665,18 @@ __device__ int wave_partition(const T* in, T* out, int s, int L, T key) {
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int x = base + u * kWave + lane;
-      const bool valid = x < end;
-      const bool lt = valid && !(key <= v[u]);
-      const bool ge = valid && !lt;
-      const uint64_t bl = __ballot(lt);
-      const uint64_t bg = __ballot(ge);
-      if (lt) out[s + cl + mbcnt(bl)] = v[u];
-      if (ge) out[end - 1 - cg - mbcnt(bg)] = v[u];
-      cl += __popcll(bl);
-      cg += __popcll(bg);
+      const int nv = min(kWave, end - (base + u * kWave));  // valid lanes of this chunk (wave-uniform)
+      if (nv > 0) {
+        const bool valid = lane < nv;
+        const bool lt = valid && !(key <= v[u]);
+        const uint64_t bl = __ballot(lt);
+        const int r = mbcnt(bl);
+        const int d = lt ? s + cl + r : end - 1 - cg - (lane - r);
+        if (valid) out[d] = v[u];
+        const int nl = __popcll(bl);
+        cl += nl;
+        cg += nv - nl;
+      }
     }
   }
   return cl;
@@ -783,7 +835,7 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
       int pushed = 0;
       uint32_t keep = 0;
       if (L <= kSmall) {
-        wave_rank_sort<T>(sm.buf[p] + s, dst + s, L, nullptr, 0);
+        lds_rank_sort<T>(sm.buf[p] + s, dst + s, L, sm.tie[threadIdx.x / kWave]);
       } else {
         const T key = sm.buf[p][s];
         const int cl = wave_partition<T>(sm.buf[p], sm.buf[p ^ 1], s, L, key);
