@@ -90,35 +90,31 @@ __device__ __forceinline__ I ld_group(I* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
+// Inclusive prefix sum across the 64 lanes of a wave, in registers: row
+// shifts by 1, 2, 4 and 8 give every lane the prefix within its 16-lane row;
+// the row broadcasts of lanes 15 and 31 then add the totals of the rows
+// before it.  Every lane of the wave must be active.
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    int u = __shfl_up(v, d, kWave);
-    if (lane >= d) v += u;
-  }
-  return v;
-}
-
-// Sum of v over the 64 lanes of a wave, returned in every lane.  Row shifts
-// by 1, 2, 4 and 8 leave each 16-lane row's sum in its last lane; the row
-// broadcasts of lanes 15 and 31 then carry it across rows, so lane 63 holds
-// the total.  Every lane of the wave must be active.
-__device__ __forceinline__ int wave_sum(int v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
   v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
   v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
   v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
   v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1 and 3
   v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2 and 3
-  return __builtin_amdgcn_readlane(v, kWave - 1);
+  return v;
 }
 
-__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
-  return v;
+// Sum of v over the 64 lanes of a wave (the last lane of the inclusive
+// scan), returned in every lane.  Every lane of the wave must be active.
+__device__ __forceinline__ int wave_sum(int v) {
+  return __builtin_amdgcn_readlane(wave_inclusive_scan(v), kWave - 1);
+}
+
+// The value v holds in lane j (j wave-uniform).
+__device__ __forceinline__ int64_t lane_read64(int64_t v, int j) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), j);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // The value v holds in lane j (j wave-uniform).
@@ -327,18 +323,17 @@ __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int3
         if (in_seg[r] && !ok) w[r] = ld_agent(a.status + j);
       }
     }
-    // nearest predecessor with a full prefix: first slot with one, lowest lane
+    // nearest predecessor with a full prefix: first slot with one, lowest
+    // lane.  The predecessors nearer than it hold their own tile's count,
+    // at most one tile's keys, so 64 of them sum in 32 bits.
 #pragma unroll
     for (int r = 0; r < kLookBack; ++r) {
       const bool pre = in_seg[r] && ((w[r] >> 40) & 3) == kFlagPre;
       const uint64_t pre_mask = __ballot(pre);
-      int64_t c = in_seg[r] ? (int64_t)(w[r] & ((1ull << 40) - 1)) : 0;
-      if (pre_mask) {
-        const int stop = __builtin_ctzll(pre_mask);
-        if (lane > stop) c = 0;
-        return excl + wave_sum64(c);
-      }
-      excl += wave_sum64(c);
+      const int stop = pre_mask ? __builtin_ctzll(pre_mask) : kWave;
+      const int64_t c = (int64_t)(w[r] & ((1ull << 40) - 1));
+      excl += wave_sum(in_seg[r] && lane < stop ? (int)c : 0);
+      if (pre_mask) return excl + lane_read64(c, stop);
     }
     base -= kWave * kLookBack;
   }
@@ -440,6 +435,7 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
   constexpr int NC = ITEMS * NW;                 // per-(item, wave) counts
   constexpr int PER = (NC + kWave - 1) / kWave;  // counts scanned per lane
   static_assert(ITEMS <= 32, "per-thread masks are 32 bits");
+  static_assert((int64_t)TILE * kWave < (1ll << 31), "the look-back sums 64 tile counts in 32 bits");
   int tid = threadIdx.x;
   // Opaque to the optimizer: keeps per-item offsets from being hoisted out of
   // the persistent loop, where they would hold dozens of registers for its
@@ -518,8 +514,8 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
       el += cl[j];
       eg += cg[j];
     }
-    const int tot_lt = __shfl(il, kWave - 1, kWave);
-    const int tot_ge = __shfl(ig, kWave - 1, kWave);
+    const int tot_lt = __builtin_amdgcn_readlane(il, kWave - 1);
+    const int tot_ge = __builtin_amdgcn_readlane(ig, kWave - 1);
     if (lane == 0)
       st_agent(a.status + tk.t, status_word(a.epoch, tidx == 0 ? kFlagPre : kFlagAgg, (uint64_t)tot_lt));
     int64_t xlt = 0;
