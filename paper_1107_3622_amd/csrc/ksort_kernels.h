@@ -266,6 +266,14 @@ struct PartSmem {
   int32_t em_slot[2], em_first[2], em_nt[2];
 };
 
+// Sub-segments of the wave queue with at most kLeaf keys are placed by rank
+// (one, two or four keys per lane) instead of being partitioned further.
+#ifndef KSORT_LEAF
+#define KSORT_LEAF 128
+#endif
+constexpr int kLeaf = KSORT_LEAF;
+static_assert(kLeaf == 64 || kLeaf == 128 || kLeaf == 256, "one, two or four keys per lane");
+
 template <typename T, int BLOCK, int CUT>
 struct FinSmem {
   static constexpr int NW = BLOCK / kWave;
@@ -275,7 +283,7 @@ struct FinSmem {
   int32_t q_head, q_tail, outstanding;
   int32_t bcnt[(CUT / BLOCK) * NW];  // workgroup partition: per-(item, wave) counts
   int32_t bc;                        // workgroup partition: smaller keys in the sub-segment
-  int32_t tie[NW][kWave];            // per wave: placement of equal keys in a leaf
+  int32_t tie[NW][kLeaf];            // per wave: placement of equal keys in a leaf
 };
 
 template <typename T, int BLOCK, int ITEMS, int CUT>
@@ -616,27 +624,50 @@ __device__ void wave_rank_sort(const In* in, T* out, int L, int64_t* pivot_slot,
 // c and must fill c, c+1, ...; they are equal bit for bit (total order), so
 // any assignment among them gives the same array, and an LDS atomic on a
 // per-wave counter for c hands them out.
-template <typename T>
+//
+// K keys per lane (lane + 64k) cover sub-segments of up to 64K keys.
+template <typename T, int K>
 __device__ void lds_rank_sort(const T* in, T* out, int L, int32_t* tie) {
   const int lane = lane_id();
-  const T v = lane < L ? in[lane] : T(0);
-  int rank = 0;
+  T v[K];
+  int rank[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    v[k] = lane + kWave * k < L ? in[lane + kWave * k] : T(0);
+    rank[k] = 0;
+  }
   int j = 0;
   for (; j + 8 <= L; j += 8) {
     T b[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) b[u] = in[j + u];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) rank += (int)(b[u] < v);
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int k = 0; k < K; ++k) rank[k] += (int)(b[u] < v[k]);
   }
-  for (; j < L; ++j) rank += (int)(in[j] < v);
-  if (lane >= L) rank = 0;
-  if (wave_sum(rank) != L * (L - 1) / 2) {
-    tie[lane] = 0;
+  for (; j < L; ++j) {
+    const T b = in[j];
+#pragma unroll
+    for (int k = 0; k < K; ++k) rank[k] += (int)(b < v[k]);
+  }
+  int sum = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (lane + kWave * k >= L) rank[k] = 0;
+    sum += rank[k];
+  }
+  if (wave_sum(sum) != L * (L - 1) / 2) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) tie[lane + kWave * k] = 0;
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the counters are clear before any increment
-    if (lane < L) rank += atomicAdd(&tie[rank], 1);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (lane + kWave * k < L) rank[k] += atomicAdd(&tie[rank[k]], 1);
   }
-  if (lane < L) gst<T>(out, (uint32_t)(rank * sizeof(T)), v);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (lane + kWave * k < L) gst<T>(out, (uint32_t)(rank[k] * sizeof(T)), v[k]);
 }
 
 // One partition of in[s .. s+L-1] into out[s .. s+L-1] by one wave (Steps
@@ -830,8 +861,14 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
       const int p = (e >> 1) & 1, s = (e >> 2) & 0xfff, L = (int)(e >> 14);
       int pushed = 0;
       uint32_t keep = 0;
-      if (L <= kSmall) {
-        lds_rank_sort<T>(sm.buf[p] + s, dst + s, L, sm.tie[threadIdx.x / kWave]);
+      if (L <= kLeaf) {
+        int32_t* tie = sm.tie[threadIdx.x / kWave];
+        if (L <= kWave)
+          lds_rank_sort<T, 1>(sm.buf[p] + s, dst + s, L, tie);
+        else if (kLeaf <= 2 * kWave || L <= 2 * kWave)
+          lds_rank_sort<T, (kLeaf > kWave ? 2 : 1)>(sm.buf[p] + s, dst + s, L, tie);
+        else
+          lds_rank_sort<T, kLeaf / kWave>(sm.buf[p] + s, dst + s, L, tie);
       } else {
         const T key = sm.buf[p][s];
         const int cl = wave_partition<T>(sm.buf[p], sm.buf[p ^ 1], s, L, key);
