@@ -20,6 +20,9 @@ Prints ONE JSON line:
                         this sort over Table 1's sizes
   worst_case            sorted, reversed, all-equal and four-valued inputs:
                         level passes and time
+  exact                 the same 7e6 workload sorted with every partition call
+                        leaving the paper's literal arrangement (the
+                        sequential algorithm's calls, pivots and keys)
   cpu_baseline          the literal CPU oracle on the host, one thread
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
@@ -267,6 +270,27 @@ def worstcase_leg(ksort, torch, n: int = 16_384) -> dict:
     return {"n": n, "inputs": out}
 
 
+def exact_leg(ksort, torch, src, reps: int = 3) -> dict:
+    """Whole sorts in the literal arrangement: every call, its key and its
+    pivot index are the sequential algorithm's; the call count and the first
+    pivot are reported with the time."""
+    ref = torch.sort(src)[0]
+    best = None
+    ok = True
+    for _ in range(reps):
+        t = src.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fp, ncalls, _ = ksort.ksort_sort_exact(t)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+        ok = ok and bool(torch.equal(t, ref))
+    n = src.numel()
+    return {"n": n, "ms": best * 1e3, "keys_per_s": n / best, "calls": ncalls, "first_pivot": fp,
+            "runs": reps, "verified": ok}
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
@@ -382,6 +406,9 @@ def main() -> int:
         log("worst-case leg")
         out["worst_case"] = worstcase_leg(ksort, torch)
         ok = ok and all(v["verified"] for v in out["worst_case"]["inputs"].values())
+        log("exact-arrangement leg")
+        out["exact"] = exact_leg(ksort, torch, synth.torch_fill(w["kind"], w["seed"], n, dev))
+        ok = ok and out["exact"]["verified"]
         ok = ok and out["batched"]["verified"] and out["serve"]["verified"]
     if not args.no_cpu:
         log("timing the CPU oracle")

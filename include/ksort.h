@@ -124,6 +124,51 @@ KSORT_API int ksort_partition_level(int dtype, const void *d_in, void *d_out, in
                           int64_t nseg, int64_t *d_pivot, void *stream);
 
 /* ------------------------------------------------------------------------
+ * The literal arrangement (Section 1.1, Steps 1-4 exactly as the sequential
+ * steps leave the array).
+ *
+ * ksort_partition_level_exact: as ksort_partition_level, except that
+ *   d_out[left..right] is exactly the array the paper's Steps 1-4 leave for
+ *   each segment, not only the same pivot index and sides: with c the count
+ *   of smaller keys, i = left + c and m = i + 1 if i < right and
+ *   d_in[i+1] >= key (else m = i), the key goes to i and the first key >= key
+ *   in (left, m] (the Step-3.1 temp) to i + 1, a smaller key at x <= m to
+ *   x - 1, a larger-or-equal key at x > m stays, and the k-th key >= key in
+ *   (left, m] (k >= 2) trades places with the (k-1)-th smaller key in
+ *   (m, right] counted from the right (which goes to q_k - 1).
+ *   Segments of one key are calls too (d_out[left] = key, pivot left).
+ *   Overlapping segments are rejected with KSORT_EINVAL (nothing is
+ *   written); invalid segments are skipped as in ksort_partition_level.
+ *   n < 2^31.  The segment arrays are read back to the host and the call
+ *   synchronizes the stream; device scratch of about 3n * 4 + 2n *
+ *   sizeof(key) bytes is allocated and freed inside the call.
+ *
+ * ksort_sort_exact: Steps 1-6 on d_data[0..n-1], in place, every partition
+ *   call leaving the literal arrangement, so every call (its segment, key
+ *   and pivot index) is the one the sequential algorithm makes; calls on
+ *   the sides of a level run together (breadth-first) instead of depth-first,
+ *   which changes no call.  A side is partitioned further when it holds two
+ *   or more keys (Steps 5-6).
+ *   d_first_pivot : device int64, nullable: i of the call on [0, n-1]
+ *                   (0 for n == 1, -1 for n == 0).
+ *   d_calls       : device int64 array of 3 * calls_cap entries, nullable;
+ *                   receives (left, right, i) of up to calls_cap calls in no
+ *                   particular order.
+ *   d_ncalls      : device int64, required with d_calls (else nullable):
+ *                   the total number of calls (may exceed calls_cap).
+ *   The call synchronizes the stream once per level (the level count is the
+ *   recursion depth: about 2.5 log2 n on random keys, n on sorted input) and
+ *   allocates about 5n * 4 + 4n * sizeof(key) bytes of device scratch for
+ *   its duration.  n < 2^31.
+ * Errors: KSORT_EINVAL (bad dtype, n < 0 or >= 2^31, null data with n > 0,
+ * d_calls without d_ncalls), KSORT_ENOMEM, KSORT_EHIP, KSORT_EUNSUPPORTED. */
+KSORT_API int ksort_partition_level_exact(int dtype, const void *d_in, void *d_out, int64_t n,
+                                const int64_t *d_seg_left, const int64_t *d_seg_len,
+                                int64_t nseg, int64_t *d_pivot, void *stream);
+KSORT_API int ksort_sort_exact(int dtype, void *d_data, int64_t n, int64_t *d_first_pivot,
+                     int64_t *d_calls, int64_t calls_cap, int64_t *d_ncalls, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched sort: Steps 1-6 on each array of a packed batch.
  *
  * Array u is d_packed[d_offsets[u] .. d_offsets[u+1]-1]; each is sorted on

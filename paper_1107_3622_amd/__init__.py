@@ -14,12 +14,14 @@ from .ksort import (  # noqa: F401
     ksort_f64,
     ksort_get_default,
     ksort_partition_level,
+    ksort_partition_level_exact,
     ksort_profile_enable,
     ksort_profile_read,
     ksort_release_workspaces,
     ksort_segmented,
     ksort_set_default,
     ksort_sort_ex,
+    ksort_sort_exact,
     ksort_variants,
     ksort_version,
     ksort_workspace_bytes,

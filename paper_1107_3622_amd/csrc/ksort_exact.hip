@@ -1,0 +1,522 @@
+// The literal arrangement of Steps 1-4 (arXiv 1107.3622, Section 1.1) on
+// the GPU, one level at a time.
+//
+// The fast path places the keys of each side in an order of its own; here
+// every level leaves exactly the array the sequential steps leave, so every
+// later key, call and pivot index is the paper's.  The arrangement of one
+// call on [left, right] with key = a[left] has a closed form:
+//   c = #{x in (left, right] : a[x] < key} and i = left + c (Step-4);
+//   m = i + 1 if i < right and a[i+1] >= key, else m = i;
+//   q_1 < q_2 < ... are the positions in (left, m] holding a key >= key and
+//   r_1 > r_2 > ... the positions in (m, right] holding a key < key (there
+//   are as many as q's, or one fewer);
+//   the key goes to i and a[q_1] (the Step-3.1 temp) to i + 1; a smaller key
+//   at x <= m moves to x - 1; a larger-or-equal key at x > m stays; a[q_k]
+//   goes to r_{k-1} (k >= 2) and a[r_k] to q_k - 1.
+// (Step-3.2 shifts the smaller keys met before the scan and the descending
+// pointer cross down by one; Step-3.1 swaps each larger key it meets there
+// with the smaller key the descending pointer found, Hoare-style.)
+//
+// Everything follows from one number per position: the count of smaller
+// keys from its segment's start up to it (a segmented scan).  A level is
+//   scan_reduce / scan_blocks / scan_apply : that count, in ltp[];
+//   move_kernel : keys that shift or stay, and the q and r keys filed by rank;
+//   pair_kernel : q_k -> r_{k-1} and r_k -> q_k - 1, the call record, and the
+//                 segments of the next level (Steps 5-6).
+// Per position the state is hd[x], the first position of its segment (-1 if
+// the key is final or outside every segment), and, at a segment's first
+// position, ln[x], its length.  Positions are 32-bit: n < 2^31.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ksort_engine.h"
+
+namespace ksort {
+namespace exact {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kSpan = kThreads * kItems;  // positions per scan block
+constexpr int kScanThreads = 1024;        // the one workgroup that scans the block totals
+
+template <typename T>
+struct LevelArgs {
+  const T* cur;            // keys before this level
+  T* nxt;                  // keys after it
+  const int32_t* hd;       // segment start of each position, or -1
+  const int32_t* ln;       // length, at segment starts
+  int32_t* hd2;            // next level (sort mode only)
+  int32_t* ln2;
+  int32_t* ltp;            // smaller keys from the segment start through the position
+  int32_t* qpos;           // position of q_k, at segment start + k
+  int32_t* rpos;           // position of r_k, at segment start + k
+  T* qkey;
+  T* rkey;
+  int32_t* bflag;          // per scan block: a segment starts in it
+  int32_t* bsum;           // per scan block: smaller keys after its last segment start
+  int32_t* carry;          // per scan block: smaller keys carried into its first position
+  int64_t n;
+  int32_t nblocks;
+  int32_t sort_mode;       // 1: whole-array sort (final keys copied, next level built)
+  int32_t* piv_at;         // level mode: i of the segment starting at each position
+  int64_t* calls;          // (left, right, i) per call, in no particular order
+  int64_t calls_cap;
+  unsigned long long* ncalls;
+  int64_t* first_pivot;    // set by the call on [0, n-1] when not null
+  unsigned long long* active;  // positions in segments of two or more keys next level
+};
+
+// (flag, sum) pairs: a flag starts a new run; sum counts smaller keys.
+struct Run {
+  int f, s;
+};
+__device__ __forceinline__ Run join(Run a, Run b) { return Run{a.f | b.f, b.f ? b.s : a.s + b.s}; }
+
+// The pair of position x: a segment start (or a final key) begins a run and
+// counts nothing; any other position counts 1 if its key is smaller than
+// its segment's key.  Comparisons are exactly `key <= a[x]` (ties go right).
+template <typename T>
+__device__ __forceinline__ Run pos_run(const LevelArgs<T>& a, int64_t x) {
+  if (x >= a.n) return Run{1, 0};
+  const int32_t h = a.hd[x];
+  if (h < 0 || h == x) return Run{1, 0};
+  return Run{0, !(a.cur[h] <= a.cur[x]) ? 1 : 0};
+}
+
+// Inclusive scan of Run pairs across the workgroup (Hillis-Steele in LDS).
+template <int N>
+__device__ Run block_scan(Run r, int* sf, int* ss) {
+  const int t = threadIdx.x;
+  sf[t] = r.f;
+  ss[t] = r.s;
+  __syncthreads();
+  for (int d = 1; d < N; d <<= 1) {
+    Run o = r;
+    if (t >= d) o = join(Run{sf[t - d], ss[t - d]}, r);
+    __syncthreads();
+    sf[t] = o.f;
+    ss[t] = o.s;
+    r = o;
+    __syncthreads();
+  }
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_reduce(LevelArgs<T> a) {
+  __shared__ int sf[kThreads], ss[kThreads];
+  const int64_t base = (int64_t)blockIdx.x * kSpan + (int64_t)threadIdx.x * kItems;
+  Run r{0, 0};
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) r = join(r, pos_run(a, base + j));
+  r = block_scan<kThreads>(r, sf, ss);
+  if (threadIdx.x == kThreads - 1) {
+    a.bflag[blockIdx.x] = r.f;
+    a.bsum[blockIdx.x] = r.s;
+  }
+}
+
+// One workgroup: the run carried into each scan block.
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_blocks(LevelArgs<T> a) {
+  __shared__ int sf[kScanThreads], ss[kScanThreads];
+  const int nb = a.nblocks;
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int b0 = threadIdx.x * per;
+  Run r{0, 0};
+  for (int b = b0; b < min(nb, b0 + per); ++b) r = join(r, Run{a.bflag[b], a.bsum[b]});
+  const Run inc = block_scan<kScanThreads>(r, sf, ss);
+  Run run = threadIdx.x > 0 ? Run{sf[threadIdx.x - 1], ss[threadIdx.x - 1]} : Run{0, 0};
+  for (int b = b0; b < min(nb, b0 + per); ++b) {
+    a.carry[b] = run.s;
+    run = join(run, Run{a.bflag[b], a.bsum[b]});
+  }
+  (void)inc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_apply(LevelArgs<T> a) {
+  __shared__ int sf[kThreads], ss[kThreads];
+  const int64_t base = (int64_t)blockIdx.x * kSpan + (int64_t)threadIdx.x * kItems;
+  Run rs[kItems];
+  Run r{0, 0};
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    rs[j] = pos_run(a, base + j);
+    r = join(r, rs[j]);
+  }
+  const Run inc = block_scan<kThreads>(r, sf, ss);
+  Run run = join(Run{0, a.carry[blockIdx.x]},
+                 threadIdx.x > 0 ? Run{sf[threadIdx.x - 1], ss[threadIdx.x - 1]} : Run{0, 0});
+  (void)inc;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    run = join(run, rs[j]);
+    if (base + j < a.n) a.ltp[base + j] = run.s;
+  }
+}
+
+// The quantities of the call on the segment starting at h.
+template <typename T>
+struct Call {
+  int64_t left, right, c, i, m;
+  T key;
+};
+template <typename T>
+__device__ __forceinline__ Call<T> call_of(const LevelArgs<T>& a, int32_t h) {
+  Call<T> k;
+  k.left = h;
+  k.right = h + (int64_t)a.ln[h] - 1;
+  k.key = a.cur[h];
+  k.c = a.ltp[k.right];
+  k.i = k.left + k.c;
+  k.m = (k.i < k.right && k.key <= a.cur[k.i + 1]) ? k.i + 1 : k.i;
+  return k;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void move_kernel(LevelArgs<T> a) {
+  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < a.n; x += (int64_t)gridDim.x * kThreads) {
+    const int32_t h = a.hd[x];
+    if (h < 0) {
+      if (a.sort_mode) a.nxt[x] = a.cur[x];
+      continue;
+    }
+    const Call<T> k = call_of(a, h);
+    if (x == k.left) {
+      a.nxt[k.i] = k.key;
+      continue;
+    }
+    const T v = a.cur[x];
+    const bool lt = !(k.key <= v);
+    if (x <= k.m) {
+      if (lt) {
+        a.nxt[x - 1] = v;
+      } else {
+        const int64_t r = (x - k.left) - a.ltp[x];  // rank among the keys >= key in (left, x]
+        if (r == 1)
+          a.nxt[k.i + 1] = v;
+        else
+          a.qkey[k.left + r] = v;
+        a.qpos[k.left + r] = (int32_t)x;
+      }
+    } else {
+      if (!lt) {
+        a.nxt[x] = v;
+      } else {
+        const int64_t r = k.c - a.ltp[x] + 1;  // rank among the smaller keys in [x, right]
+        a.rpos[k.left + r] = (int32_t)x;
+        a.rkey[k.left + r] = v;
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
+  unsigned long long act = 0;
+  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < a.n; x += (int64_t)gridDim.x * kThreads) {
+    const int32_t h = a.hd[x];
+    if (h < 0) {
+      if (a.sort_mode) a.hd2[x] = -1;
+      continue;
+    }
+    const Call<T> k = call_of(a, h);
+    const int64_t nq = (k.m - k.left) - a.ltp[k.m];  // keys >= key in (left, m]
+    const int64_t nr = k.c - a.ltp[k.m];             // smaller keys in (m, right]
+    const int64_t r = x - k.left;
+    // (the slots read here were filed by move_kernel in this level: the
+    // closed form has nr = nq or nq - 1; the range checks only keep a
+    // corrupted slot from writing outside the segment)
+    if (r >= 2 && r <= nq) {
+      const int64_t to = a.rpos[k.left + r - 1];
+      if (to > k.left && to <= k.right) a.nxt[to] = a.qkey[k.left + r];
+    }
+    if (r >= 1 && r <= nr) {
+      const int64_t to = (int64_t)a.qpos[k.left + r] - 1;
+      if (to >= k.left && to <= k.right) a.nxt[to] = a.rkey[k.left + r];
+    }
+    if (r == 0) {
+      if (a.ncalls) {
+        const unsigned long long j = atomicAdd(a.ncalls, 1ull);
+        if (a.calls && (int64_t)j < a.calls_cap) {
+          a.calls[3 * j] = k.left;
+          a.calls[3 * j + 1] = k.right;
+          a.calls[3 * j + 2] = k.i;
+        }
+      }
+      if (a.piv_at) a.piv_at[k.left] = (int32_t)k.i;
+      if (a.first_pivot && k.left == 0 && k.right == a.n - 1) *a.first_pivot = k.i;
+    }
+    if (a.sort_mode) {
+      // Steps 5-6: [left, i-1] and [i+1, right] go on if they hold two or more keys
+      int32_t nh = -1;
+      if (x < k.i && k.c >= 2) nh = (int32_t)k.left;
+      if (x > k.i && k.right - k.i >= 2) nh = (int32_t)(k.i + 1);
+      a.hd2[x] = nh;
+      if (nh == x) a.ln2[x] = (int32_t)(x == k.left ? k.c : k.right - k.i);
+      act += nh >= 0;
+    }
+  }
+  if (a.sort_mode) {
+    // one global atomic per workgroup
+    __shared__ unsigned long long wsum;
+    if (threadIdx.x == 0) wsum = 0;
+    __syncthreads();
+    if (act) atomicAdd(&wsum, act);
+    __syncthreads();
+    if (threadIdx.x == 0 && wsum) atomicAdd(a.active, wsum);
+  }
+}
+
+// Whole array as one segment (sort mode, n >= 2).
+__global__ __launch_bounds__(kThreads) void init_whole(int32_t* hd, int32_t* ln, int64_t n) {
+  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) {
+    hd[x] = 0;
+    if (x == 0) ln[0] = (int32_t)n;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < n; x += (int64_t)gridDim.x * kThreads) p[x] = v;
+}
+
+// Level mode: chunk j covers positions [cs[j], cs[j] + kSpan) of segment
+// (cl[j], clen[j]).
+__global__ __launch_bounds__(kThreads) void mark_segments(int32_t* hd, int32_t* ln, const int64_t* cl,
+                                                            const int64_t* clen, const int64_t* cs) {
+  const int64_t left = cl[blockIdx.x], len = clen[blockIdx.x], s0 = cs[blockIdx.x];
+  const int64_t end = min(left + len, s0 + (int64_t)kSpan);
+  for (int64_t x = s0 + threadIdx.x; x < end; x += kThreads) {
+    hd[x] = (int32_t)left;
+    if (x == left) ln[x] = (int32_t)len;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void gather_pivots(const int32_t* piv_at, const int64_t* left,
+                                                            const uint8_t* ok, int64_t nseg, int64_t* out) {
+  for (int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x; s < nseg; s += (int64_t)gridDim.x * kThreads)
+    if (ok[s]) out[s] = piv_at[left[s]];
+}
+
+// ------------------------------------------------------------------ host
+
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 4096)); }
+
+// Device buffers of one run, freed on scope exit.
+struct Buffers {
+  std::vector<void*> ptrs;
+  ~Buffers() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename P>
+  int take(P** out, size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(P));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    ptrs.push_back(p);
+    *out = (P*)p;
+    return KSORT_OK;
+  }
+};
+
+// Buffers of a level; hd[1] and ln[1] (the next level's) only in sort mode.
+template <typename T>
+static int alloc_level(Buffers& B, LevelArgs<T>& a, int64_t n, bool sort_mode, int32_t* hd[2], int32_t* ln[2]) {
+  int rc = 0;
+  const int64_t nb = (n + kSpan - 1) / kSpan;
+  a.n = n;
+  a.nblocks = (int32_t)nb;
+  hd[1] = ln[1] = nullptr;
+  if ((rc = B.take(&hd[0], (size_t)n)) || (rc = B.take(&ln[0], (size_t)n)) || (rc = B.take(&a.ltp, (size_t)n)) ||
+      (rc = B.take(&a.qpos, (size_t)n)) || (rc = B.take(&a.rpos, (size_t)n)) || (rc = B.take(&a.qkey, (size_t)n)) ||
+      (rc = B.take(&a.rkey, (size_t)n)) || (rc = B.take(&a.bflag, (size_t)nb)) || (rc = B.take(&a.bsum, (size_t)nb)) ||
+      (rc = B.take(&a.carry, (size_t)nb)))
+    return rc;
+  if (sort_mode) {
+    if ((rc = B.take(&hd[1], (size_t)n)) || (rc = B.take(&ln[1], (size_t)n)) || (rc = B.take(&a.active, 1))) return rc;
+  }
+  a.hd = hd[0];
+  a.ln = ln[0];
+  a.hd2 = hd[1];
+  a.ln2 = ln[1];
+  return KSORT_OK;
+}
+
+template <typename T>
+static int launch_level(const LevelArgs<T>& a, hipStream_t st) {
+  const int nb = a.nblocks;
+  scan_reduce<T><<<nb, kThreads, 0, st>>>(a);
+  scan_blocks<T><<<1, kScanThreads, 0, st>>>(a);
+  scan_apply<T><<<nb, kThreads, 0, st>>>(a);
+  move_kernel<T><<<grid_for(a.n), kThreads, 0, st>>>(a);
+  pair_kernel<T><<<grid_for(a.n), kThreads, 0, st>>>(a);
+  KSORT_HIP(hipGetLastError());
+  return KSORT_OK;
+}
+
+static int check_device() {
+  int dev = 0;
+  KSORT_HIP(hipGetDevice(&dev));
+  const DeviceInfo* di = nullptr;
+  int rc = device_info(dev, &di);
+  if (rc) return rc;
+  if (!di->gfx950) return fail(KSORT_EUNSUPPORTED, "device is " + di->arch + ", not gfx950");
+  return KSORT_OK;
+}
+
+// The number of scan blocks one workgroup totals in scan_blocks is bounded
+// by its per-thread loop, not by a fixed array: any n below 2^31 works.
+template <typename T>
+static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_calls, int64_t calls_cap,
+                      int64_t* d_ncalls, hipStream_t st) {
+  if (d_ncalls) KSORT_HIP(hipMemsetAsync(d_ncalls, 0, sizeof(int64_t), st));
+  if (n <= 1) {
+    if (d_first_pivot) {
+      const int64_t v = n == 0 ? -1 : 0;
+      KSORT_HIP(hipMemcpyAsync(d_first_pivot, &v, sizeof v, hipMemcpyHostToDevice, st));
+      KSORT_HIP(hipStreamSynchronize(st));
+    }
+    return KSORT_OK;
+  }
+  Buffers B;
+  LevelArgs<T> a{};
+  int32_t *H[2], *Ln[2];
+  int rc = alloc_level<T>(B, a, n, true, H, Ln);
+  if (rc) return rc;
+  T* scratch = nullptr;
+  if ((rc = B.take(&scratch, (size_t)n))) return rc;
+  unsigned long long* h_active = nullptr;
+  KSORT_HIP(hipHostMalloc((void**)&h_active, sizeof(unsigned long long), hipHostMallocDefault));
+  struct HostFree {
+    void* p;
+    ~HostFree() { (void)hipHostFree(p); }
+  } hf{h_active};
+  a.sort_mode = 1;
+  a.calls = d_calls;
+  a.calls_cap = d_calls ? calls_cap : 0;
+  a.ncalls = (unsigned long long*)d_ncalls;
+  init_whole<<<grid_for(n), kThreads, 0, st>>>(H[0], Ln[0], n);
+  KSORT_HIP(hipGetLastError());
+  T* bufs[2] = {data, scratch};
+  int cur = 0;
+  // every level ends at least one key's partitioning, so n levels suffice
+  for (int64_t level = 0; level < n; ++level) {
+    a.cur = bufs[cur];
+    a.nxt = bufs[cur ^ 1];
+    a.hd = H[cur];
+    a.ln = Ln[cur];
+    a.hd2 = H[cur ^ 1];
+    a.ln2 = Ln[cur ^ 1];
+    a.first_pivot = level == 0 ? d_first_pivot : nullptr;
+    KSORT_HIP(hipMemsetAsync(a.active, 0, sizeof(unsigned long long), st));
+    if ((rc = launch_level<T>(a, st))) return rc;
+    KSORT_HIP(hipMemcpyAsync(h_active, a.active, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    KSORT_HIP(hipStreamSynchronize(st));
+    cur ^= 1;
+    if (*h_active == 0) break;
+  }
+  if (cur == 1) KSORT_HIP(hipMemcpyAsync(data, scratch, (size_t)n * sizeof(T), hipMemcpyDeviceToDevice, st));
+  KSORT_HIP(hipStreamSynchronize(st));
+  return KSORT_OK;
+}
+
+template <typename T>
+static int level_exact(const T* d_in, T* d_out, int64_t n, const int64_t* d_left, const int64_t* d_len, int64_t nseg,
+                       int64_t* d_pivot, hipStream_t st) {
+  std::vector<int64_t> hl((size_t)nseg), hn((size_t)nseg);
+  KSORT_HIP(hipMemcpyAsync(hl.data(), d_left, (size_t)nseg * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  KSORT_HIP(hipMemcpyAsync(hn.data(), d_len, (size_t)nseg * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  KSORT_HIP(hipStreamSynchronize(st));
+  std::vector<uint8_t> ok((size_t)nseg, 0);
+  std::vector<int64_t> order;
+  bool bad = false;
+  for (int64_t s = 0; s < nseg; ++s) {
+    if (hl[s] < 0 || hn[s] < 1 || hl[s] > n - hn[s]) {
+      bad = true;
+      continue;
+    }
+    ok[s] = 1;
+    order.push_back(s);
+  }
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return hl[x] < hl[y]; });
+  for (size_t j = 1; j < order.size(); ++j)
+    if (hl[order[j]] < hl[order[j - 1]] + hn[order[j - 1]]) return fail(KSORT_EINVAL, "segments overlap");
+  std::vector<int64_t> cl, clen, cs;
+  for (int64_t s : order)
+    for (int64_t p = hl[s]; p < hl[s] + hn[s]; p += kSpan) {
+      cl.push_back(hl[s]);
+      clen.push_back(hn[s]);
+      cs.push_back(p);
+    }
+  Buffers B;
+  LevelArgs<T> a{};
+  int32_t *H[2], *Ln[2];
+  int rc = alloc_level<T>(B, a, n, false, H, Ln);
+  if (rc) return rc;
+  int64_t *dcl = nullptr, *dclen = nullptr, *dcs = nullptr;
+  uint8_t* dok = nullptr;
+  if ((rc = B.take(&dcl, cl.size())) || (rc = B.take(&dclen, cl.size())) || (rc = B.take(&dcs, cl.size())) ||
+      (rc = B.take(&dok, (size_t)nseg)) || (rc = B.take(&a.piv_at, (size_t)n)))
+    return rc;
+  KSORT_HIP(hipMemcpyAsync(dcl, cl.data(), cl.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  KSORT_HIP(hipMemcpyAsync(dclen, clen.data(), clen.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  KSORT_HIP(hipMemcpyAsync(dcs, cs.data(), cs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  KSORT_HIP(hipMemcpyAsync(dok, ok.data(), ok.size(), hipMemcpyHostToDevice, st));
+  fill_i32<<<grid_for(n), kThreads, 0, st>>>(H[0], n, -1);
+  if (!cl.empty()) mark_segments<<<(unsigned)cl.size(), kThreads, 0, st>>>(H[0], Ln[0], dcl, dclen, dcs);
+  KSORT_HIP(hipGetLastError());
+  a.cur = d_in;
+  a.nxt = d_out;
+  a.sort_mode = 0;
+  if ((rc = launch_level<T>(a, st))) return rc;
+  gather_pivots<<<grid_for(nseg), kThreads, 0, st>>>(a.piv_at, d_left, dok, nseg, d_pivot);
+  KSORT_HIP(hipGetLastError());
+  KSORT_HIP(hipStreamSynchronize(st));
+  if (bad) return fail(KSORT_EINVAL, "a segment is outside [0, n) or has len < 1");
+  return KSORT_OK;
+}
+
+}  // namespace exact
+}  // namespace ksort
+
+using namespace ksort;
+
+extern "C" {
+
+int ksort_partition_level_exact(int dtype, const void* d_in, void* d_out, int64_t n, const int64_t* d_seg_left,
+                                const int64_t* d_seg_len, int64_t nseg, int64_t* d_pivot, void* stream) {
+  if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
+  if (n < 0 || nseg < 0) return fail(KSORT_EINVAL, "negative size");
+  if (n >= (int64_t)1 << 31) return fail(KSORT_EINVAL, "the exact arrangement takes n < 2^31");
+  if (nseg == 0) return KSORT_OK;
+  if (!d_in || !d_out || !d_seg_left || !d_seg_len || !d_pivot) return fail(KSORT_EINVAL, "null pointer");
+  if (d_in == d_out) return fail(KSORT_EINVAL, "d_in and d_out must not overlap");
+  int rc = exact::check_device();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == KSORT_F64)
+    return exact::level_exact<double>((const double*)d_in, (double*)d_out, n, d_seg_left, d_seg_len, nseg, d_pivot,
+                                      st);
+  return exact::level_exact<float>((const float*)d_in, (float*)d_out, n, d_seg_left, d_seg_len, nseg, d_pivot, st);
+}
+
+int ksort_sort_exact(int dtype, void* d_data, int64_t n, int64_t* d_first_pivot, int64_t* d_calls,
+                     int64_t calls_cap, int64_t* d_ncalls, void* stream) {
+  if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
+  if (n < 0 || calls_cap < 0) return fail(KSORT_EINVAL, "negative size");
+  if (n >= (int64_t)1 << 31) return fail(KSORT_EINVAL, "the exact arrangement takes n < 2^31");
+  if (n > 0 && !d_data) return fail(KSORT_EINVAL, "null data pointer");
+  if (d_calls && !d_ncalls) return fail(KSORT_EINVAL, "d_calls needs d_ncalls");
+  int rc = exact::check_device();
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (dtype == KSORT_F64)
+    return exact::sort_exact<double>((double*)d_data, n, d_first_pivot, d_calls, calls_cap, d_ncalls, st);
+  return exact::sort_exact<float>((float*)d_data, n, d_first_pivot, d_calls, calls_cap, d_ncalls, st);
+}
+
+}  // extern "C"

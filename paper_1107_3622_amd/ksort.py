@@ -74,6 +74,8 @@ SIGNATURES = {
     "ksort_sort_ex": (_int, [_int, _p, _i64, _p, _p, _p]),
     "ksort_partition_level": (_int, [_int, _p, _p, _i64, _p, _p, _i64, _p, _p]),
     "ksort_segmented": (_int, [_int, _p, _i64, _p, _i64, _p, _p, _p]),
+    "ksort_partition_level_exact": (_int, [_int, _p, _p, _i64, _p, _p, _i64, _p, _p]),
+    "ksort_sort_exact": (_int, [_int, _p, _i64, _p, _p, _i64, _p, _p]),
     "ksort_variants": (_int, [_int, _p, _int]),
     "ksort_get_default": (_int, [_int, _p]),
     "ksort_set_default": (_int, [_int, _p]),
@@ -218,6 +220,47 @@ def ksort_partition_level(d_in, d_out, seg_left, seg_len, pivots=None, stream=No
                                         seg_left.data_ptr(), seg_len.data_ptr(), nseg, pivots.data_ptr(),
                                         _stream(stream)), "ksort_partition_level")
     return pivots
+
+
+def ksort_partition_level_exact(d_in, d_out, seg_left, seg_len, pivots=None, stream=None):
+    """One partition (Steps 1-4) of each segment from d_in into d_out, leaving
+    exactly the arrangement of the paper's sequential steps.  Returns the
+    int64 device tensor of pivot indices."""
+    torch = _torch()
+    _check_keys(d_in)
+    _check_keys(d_out)
+    if d_in.dtype != d_out.dtype or d_in.numel() != d_out.numel():
+        raise ValueError("d_in and d_out must have the same dtype and size")
+    for s in (seg_left, seg_len):
+        if s.dtype != torch.int64 or not s.is_cuda or not s.is_contiguous():
+            raise ValueError("segment arrays must be contiguous int64 device tensors")
+    nseg = seg_left.numel()
+    if seg_len.numel() != nseg:
+        raise ValueError("seg_left and seg_len differ in length")
+    if pivots is None:
+        pivots = torch.empty(nseg, dtype=torch.int64, device=d_in.device)
+    _check(load().ksort_partition_level_exact(_dtype_code(d_in), d_in.data_ptr(), d_out.data_ptr(), d_in.numel(),
+                                              seg_left.data_ptr(), seg_len.data_ptr(), nseg, pivots.data_ptr(),
+                                              _stream(stream)), "ksort_partition_level_exact")
+    return pivots
+
+
+def ksort_sort_exact(t, calls_cap: int = 0, stream=None):
+    """Steps 1-6 on t in place, every call leaving the literal arrangement.
+    Returns (first pivot, total calls, (calls_cap', 3) int64 device tensor of
+    (left, right, i) per call in no particular order, or None)."""
+    torch = _torch()
+    _check_keys(t)
+    fp = torch.empty(1, dtype=torch.int64, device=t.device)
+    nc = torch.zeros(1, dtype=torch.int64, device=t.device)
+    calls = torch.empty((max(calls_cap, 1), 3), dtype=torch.int64, device=t.device) if calls_cap > 0 else None
+    _check(load().ksort_sort_exact(_dtype_code(t), t.data_ptr(), t.numel(), fp.data_ptr(),
+                                   calls.data_ptr() if calls is not None else None, calls_cap,
+                                   nc.data_ptr(), _stream(stream)), "ksort_sort_exact")
+    ncalls = int(nc.item())
+    if calls is not None:
+        calls = calls[:min(ncalls, calls_cap)]
+    return int(fp.item()), ncalls, calls
 
 
 def ksort_segmented(t, offsets, first_pivots=None, tune=None, stream=None, want_pivots=True):

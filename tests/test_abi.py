@@ -59,6 +59,14 @@ def test_host_only_calls(lib):
     b2 = ksort.ksort_workspace_bytes(ksort.KSORT_F64, 2_000_000)
     assert 8_000_000 < b1 < b2
     assert ksort.ksort_workspace_bytes(5, 10, 1) == 0
+    # the literal-arrangement entry points check their arguments before any
+    # device call
+    assert lib.ksort_sort_exact(9, None, 0, None, None, 0, None, None) == -1
+    assert lib.ksort_sort_exact(0, None, 1 << 31, None, None, 0, None, None) == -1
+    assert lib.ksort_sort_exact(0, None, 5, None, None, 0, None, None) == -1
+    assert lib.ksort_partition_level_exact(9, None, None, 10, None, None, 1, None, None) == -1
+    assert lib.ksort_partition_level_exact(0, None, None, 1 << 31, None, None, 1, None, None) == -1
+    assert lib.ksort_partition_level_exact(0, None, None, 10, None, None, 0, None, None) == 0
 
 
 def test_set_default_rejects_unknown_variant(lib):
