@@ -76,6 +76,7 @@ struct Workspace {
   Seg* fin[2] = {nullptr, nullptr};
   uint64_t* status = nullptr;
   int64_t* stage_keys = nullptr;
+  bool stats = false;          // this run keeps per-level key counts (profiling)
   int32_t* pending = nullptr;
   int32_t* done_stage = nullptr;
   uint32_t epoch = 0;         // last epoch used

@@ -990,7 +990,7 @@ __global__ void clear_kernel(uint64_t* p, int64_t n) {
 }
 
 // Clears counters and flags before a run.
-__global__ void reset_kernel(StageCtr* ctr, Flags* flags, int64_t* stage_keys, int32_t cap_stats) {
+__global__ void reset_kernel(StageCtr* ctr, Flags* flags) {
   const int tid = threadIdx.x;
   if (tid < 3) {
     ctr[tid].nseg = 0;
@@ -1004,8 +1004,6 @@ __global__ void reset_kernel(StageCtr* ctr, Flags* flags, int64_t* stage_keys, i
     flags->err = 0;
     flags->overflow = 0;
   }
-  if (stage_keys)
-    for (int j = tid; j < 2 * cap_stats; j += blockDim.x) stage_keys[j] = 0;
 }
 
 // One block per input array (or per segment in single-level mode): validate,

@@ -285,7 +285,7 @@ StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_
   a.pending = nullptr;
   a.done_stage = nullptr;
   a.flags = ws.flags;
-  a.stage_keys = ws.stage_keys;
+  a.stage_keys = ws.stats ? ws.stage_keys : nullptr;  // counted only for profiling
   a.cap_live = (int32_t)ws.caps.live;
   a.cap_tiles = (int32_t)ws.caps.tiles;
   // A stage's finish list holds the children of the stage before below
@@ -338,7 +338,13 @@ int launch_reset(Workspace& ws) {
   const int blocks = (int)std::min<int64_t>(1024, (nwords + 255) / 256);
   hipLaunchKernelGGL(clear_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, ws.stream, ws.status, nwords);
   KSORT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, ws.stream, ws.ctr, ws.flags, ws.stage_keys, ws.cap_stats);
+  if (ws.stats) {
+    const int64_t nk = 2 * (int64_t)ws.cap_stats;
+    hipLaunchKernelGGL(clear_kernel, dim3((unsigned)std::min<int64_t>(256, (nk + 255) / 256)), dim3(256), 0, ws.stream,
+                       (uint64_t*)ws.stage_keys, nk);
+    KSORT_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, ws.stream, ws.ctr, ws.flags);
   KSORT_HIP(hipGetLastError());
   return KSORT_OK;
 }
@@ -471,6 +477,7 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
   if (rc) return rc;
   const int grid = stage_grid(*v, *di, ws.caps);
   const bool prof = profiling_on();
+  ws.stats = prof;
   const int64_t call = next_call_id();
 
   int stage = 0;
@@ -621,6 +628,7 @@ static int run_level(int dtype, const void* d_in, void* d_out, int64_t n, const 
   std::lock_guard<std::mutex> lk(ws.mu);
   const Caps caps = caps_for(*v, n, nseg, true);
   rc = ws.reserve(caps, 0);
+  ws.stats = false;
   if (rc) return rc;
   rc = launch_reset(ws);
   if (rc) return rc;
