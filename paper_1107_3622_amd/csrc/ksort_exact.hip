@@ -54,6 +54,7 @@ struct LevelArgs {
   int32_t* rpos;           // position of r_k, at segment start + k
   T* qkey;
   T* rkey;
+  uint8_t* fl;             // per position: bit 0 starts a run, bit 1 a smaller key (nblocks * kSpan)
   int32_t* bflag;          // per scan block: a segment starts in it
   int32_t* bsum;           // per scan block: smaller keys after its last segment start
   int32_t* carry;          // per scan block: smaller keys carried into its first position
@@ -66,7 +67,20 @@ struct LevelArgs {
   unsigned long long* ncalls;
   int64_t* first_pivot;    // set by the call on [0, n-1] when not null
   unsigned long long* active;  // positions in segments of two or more keys next level
+  // sort mode: per scan block, whether any of its positions is in a segment
+  // at this level, at the level before, and (written here) at the next one;
+  // null in level mode (nothing is skipped)
+  const uint8_t* act;
+  const uint8_t* act_prev;
+  uint8_t* act_next;
 };
+
+// A block whose positions are all final at this level and the one before
+// holds the same keys and segment state in both buffers: nothing to do.
+template <typename T>
+__device__ __forceinline__ bool block_idle(const LevelArgs<T>& a, int64_t b) {
+  return a.act && !a.act[b] && !a.act_prev[b];
+}
 
 // (flag, sum) pairs: a flag starts a new run; sum counts smaller keys.
 struct Run {
@@ -104,13 +118,50 @@ __device__ Run block_scan(Run r, int* sf, int* ss) {
   return r;
 }
 
+// Each thread takes kItems consecutive positions; their flags are kept as one
+// 16-byte word for scan_apply.
+static_assert(kItems == 16, "one 16-byte flag word per thread");
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void scan_reduce(LevelArgs<T> a) {
   __shared__ int sf[kThreads], ss[kThreads];
+  if (a.act) {
+    if (threadIdx.x == 0) a.act_next[blockIdx.x] = 0;
+    if (!a.act[blockIdx.x]) {  // every position final: a run start that counts nothing
+      if (threadIdx.x == 0) {
+        a.bflag[blockIdx.x] = 1;
+        a.bsum[blockIdx.x] = 0;
+      }
+      return;
+    }
+  }
   const int64_t base = (int64_t)blockIdx.x * kSpan + (int64_t)threadIdx.x * kItems;
   Run r{0, 0};
+  uint32_t w[4] = {0, 0, 0, 0};
+  if (base + kItems <= a.n) {
+    int32_t h[kItems];
+    T v[kItems];
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) r = join(r, pos_run(a, base + j));
+    for (int j = 0; j < kItems; ++j) {
+      h[j] = a.hd[base + j];
+      v[j] = a.cur[base + j];
+    }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const bool start = h[j] < 0 || h[j] == base + j;
+      const bool lt = !start && !(a.cur[h[j]] <= v[j]);
+      r = join(r, Run{start ? 1 : 0, lt ? 1 : 0});
+      w[j / 4] |= (uint32_t)((start ? 1 : 0) | (lt ? 2 : 0)) << (8 * (j % 4));
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const Run p = pos_run(a, base + j);
+      r = join(r, p);
+      w[j / 4] |= (uint32_t)(p.f | (p.s << 1)) << (8 * (j % 4));
+    }
+  }
+  *(uint4*)(a.fl + base) = make_uint4(w[0], w[1], w[2], w[3]);
   r = block_scan<kThreads>(r, sf, ss);
   if (threadIdx.x == kThreads - 1) {
     a.bflag[blockIdx.x] = r.f;
@@ -139,22 +190,36 @@ __global__ __launch_bounds__(kScanThreads) void scan_blocks(LevelArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void scan_apply(LevelArgs<T> a) {
   __shared__ int sf[kThreads], ss[kThreads];
+  if (a.act && !a.act[blockIdx.x]) return;  // counts are read only inside segments
   const int64_t base = (int64_t)blockIdx.x * kSpan + (int64_t)threadIdx.x * kItems;
+  const uint4 wv = *(const uint4*)(a.fl + base);
+  const uint32_t w[4] = {wv.x, wv.y, wv.z, wv.w};
   Run rs[kItems];
   Run r{0, 0};
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    rs[j] = pos_run(a, base + j);
+    const uint32_t b = (w[j / 4] >> (8 * (j % 4))) & 3u;
+    rs[j] = Run{(int)(b & 1u), (int)(b >> 1)};
     r = join(r, rs[j]);
   }
   const Run inc = block_scan<kThreads>(r, sf, ss);
   Run run = join(Run{0, a.carry[blockIdx.x]},
                  threadIdx.x > 0 ? Run{sf[threadIdx.x - 1], ss[threadIdx.x - 1]} : Run{0, 0});
   (void)inc;
+  int32_t out[kItems];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     run = join(run, rs[j]);
-    if (base + j < a.n) a.ltp[base + j] = run.s;
+    out[j] = run.s;
+  }
+  if (base + kItems <= a.n) {
+#pragma unroll
+    for (int q = 0; q < kItems / 4; ++q)
+      *(int4*)(a.ltp + base + 4 * q) = make_int4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+      if (base + j < a.n) a.ltp[base + j] = out[j];
   }
 }
 
@@ -179,9 +244,12 @@ __device__ __forceinline__ Call<T> call_of(const LevelArgs<T>& a, int32_t h) {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void move_kernel(LevelArgs<T> a) {
   for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < a.n; x += (int64_t)gridDim.x * kThreads) {
+    if (block_idle(a, x / kSpan)) continue;
     const int32_t h = a.hd[x];
     if (h < 0) {
-      if (a.sort_mode) a.nxt[x] = a.cur[x];
+      // a key that became final in the level before is copied once; both
+      // buffers hold it from then on (hd2 still holds that level's state)
+      if (a.sort_mode && (!a.act || a.hd2[x] >= 0)) a.nxt[x] = a.cur[x];
       continue;
     }
     const Call<T> k = call_of(a, h);
@@ -216,8 +284,9 @@ __global__ __launch_bounds__(kThreads) void move_kernel(LevelArgs<T> a) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
-  unsigned long long act = 0;
+  unsigned long long act = 0, ncall = 0;
   for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < a.n; x += (int64_t)gridDim.x * kThreads) {
+    if (block_idle(a, x / kSpan)) continue;
     const int32_t h = a.hd[x];
     if (h < 0) {
       if (a.sort_mode) a.hd2[x] = -1;
@@ -239,13 +308,17 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
       if (to >= k.left && to <= k.right) a.nxt[to] = a.rkey[k.left + r];
     }
     if (r == 0) {
-      if (a.ncalls) {
+      // a call: with records wanted, each takes a slot (and so is counted);
+      // otherwise calls are only counted, one atomic per workgroup
+      if (a.calls) {
         const unsigned long long j = atomicAdd(a.ncalls, 1ull);
-        if (a.calls && (int64_t)j < a.calls_cap) {
+        if ((int64_t)j < a.calls_cap) {
           a.calls[3 * j] = k.left;
           a.calls[3 * j + 1] = k.right;
           a.calls[3 * j + 2] = k.i;
         }
+      } else {
+        ++ncall;
       }
       if (a.piv_at) a.piv_at[k.left] = (int32_t)k.i;
       if (a.first_pivot && k.left == 0 && k.right == a.n - 1) *a.first_pivot = k.i;
@@ -258,16 +331,19 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
       a.hd2[x] = nh;
       if (nh == x) a.ln2[x] = (int32_t)(x == k.left ? k.c : k.right - k.i);
       act += nh >= 0;
+      if (nh >= 0 && a.act_next) a.act_next[x / kSpan] = 1;
     }
   }
-  if (a.sort_mode) {
-    // one global atomic per workgroup
-    __shared__ unsigned long long wsum;
-    if (threadIdx.x == 0) wsum = 0;
-    __syncthreads();
-    if (act) atomicAdd(&wsum, act);
-    __syncthreads();
-    if (threadIdx.x == 0 && wsum) atomicAdd(a.active, wsum);
+  // one global atomic per workgroup for each count
+  __shared__ unsigned long long wsum[2];
+  if (threadIdx.x < 2) wsum[threadIdx.x] = 0;
+  __syncthreads();
+  if (act) atomicAdd(&wsum[0], act);
+  if (ncall) atomicAdd(&wsum[1], ncall);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (a.sort_mode && wsum[0]) atomicAdd(a.active, wsum[0]);
+    if (a.ncalls && wsum[1]) atomicAdd(a.ncalls, wsum[1]);
   }
 }
 
@@ -333,7 +409,8 @@ static int alloc_level(Buffers& B, LevelArgs<T>& a, int64_t n, bool sort_mode, i
   hd[1] = ln[1] = nullptr;
   if ((rc = B.take(&hd[0], (size_t)n)) || (rc = B.take(&ln[0], (size_t)n)) || (rc = B.take(&a.ltp, (size_t)n)) ||
       (rc = B.take(&a.qpos, (size_t)n)) || (rc = B.take(&a.rpos, (size_t)n)) || (rc = B.take(&a.qkey, (size_t)n)) ||
-      (rc = B.take(&a.rkey, (size_t)n)) || (rc = B.take(&a.bflag, (size_t)nb)) || (rc = B.take(&a.bsum, (size_t)nb)) ||
+      (rc = B.take(&a.rkey, (size_t)n)) || (rc = B.take(&a.fl, (size_t)nb * kSpan)) ||
+      (rc = B.take(&a.bflag, (size_t)nb)) || (rc = B.take(&a.bsum, (size_t)nb)) ||
       (rc = B.take(&a.carry, (size_t)nb)))
     return rc;
   if (sort_mode) {
@@ -395,6 +472,9 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
     void* p;
     ~HostFree() { (void)hipHostFree(p); }
   } hf{h_active};
+  uint8_t* act_ring = nullptr;  // three levels of per-block activity flags
+  if ((rc = B.take(&act_ring, (size_t)3 * a.nblocks))) return rc;
+  KSORT_HIP(hipMemsetAsync(act_ring, 1, (size_t)3 * a.nblocks, st));
   a.sort_mode = 1;
   a.calls = d_calls;
   a.calls_cap = d_calls ? calls_cap : 0;
@@ -411,6 +491,9 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
     a.ln = Ln[cur];
     a.hd2 = H[cur ^ 1];
     a.ln2 = Ln[cur ^ 1];
+    a.act = act_ring + (size_t)(level % 3) * a.nblocks;
+    a.act_prev = act_ring + (size_t)((level + 2) % 3) * a.nblocks;
+    a.act_next = act_ring + (size_t)((level + 1) % 3) * a.nblocks;
     a.first_pivot = level == 0 ? d_first_pivot : nullptr;
     KSORT_HIP(hipMemsetAsync(a.active, 0, sizeof(unsigned long long), st));
     if ((rc = launch_level<T>(a, st))) return rc;
