@@ -483,23 +483,31 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
   KSORT_HIP(hipGetLastError());
   T* bufs[2] = {data, scratch};
   int cur = 0;
-  // every level ends at least one key's partitioning, so n levels suffice
-  for (int64_t level = 0; level < n; ++level) {
-    a.cur = bufs[cur];
-    a.nxt = bufs[cur ^ 1];
-    a.hd = H[cur];
-    a.ln = Ln[cur];
-    a.hd2 = H[cur ^ 1];
-    a.ln2 = Ln[cur ^ 1];
-    a.act = act_ring + (size_t)(level % 3) * a.nblocks;
-    a.act_prev = act_ring + (size_t)((level + 2) % 3) * a.nblocks;
-    a.act_next = act_ring + (size_t)((level + 1) % 3) * a.nblocks;
-    a.first_pivot = level == 0 ? d_first_pivot : nullptr;
-    KSORT_HIP(hipMemsetAsync(a.active, 0, sizeof(unsigned long long), st));
-    if ((rc = launch_level<T>(a, st))) return rc;
+  // Levels are launched in groups between reads of the active count; a
+  // level after the last one finds every block idle.  Every level ends with
+  // a complete array in its output buffer (keys final for two levels are in
+  // both buffers, keys final since the level before are copied once).
+  // Every level ends at least one key's partitioning, so n levels suffice.
+  constexpr int kGroup = 8;
+  for (int64_t level = 0; level < n;) {
+    const int64_t stop = std::min<int64_t>(n, level + kGroup);
+    for (; level < stop; ++level) {
+      a.cur = bufs[cur];
+      a.nxt = bufs[cur ^ 1];
+      a.hd = H[cur];
+      a.ln = Ln[cur];
+      a.hd2 = H[cur ^ 1];
+      a.ln2 = Ln[cur ^ 1];
+      a.act = act_ring + (size_t)(level % 3) * a.nblocks;
+      a.act_prev = act_ring + (size_t)((level + 2) % 3) * a.nblocks;
+      a.act_next = act_ring + (size_t)((level + 1) % 3) * a.nblocks;
+      a.first_pivot = level == 0 ? d_first_pivot : nullptr;
+      KSORT_HIP(hipMemsetAsync(a.active, 0, sizeof(unsigned long long), st));
+      if ((rc = launch_level<T>(a, st))) return rc;
+      cur ^= 1;
+    }
     KSORT_HIP(hipMemcpyAsync(h_active, a.active, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     KSORT_HIP(hipStreamSynchronize(st));
-    cur ^= 1;
     if (*h_active == 0) break;
   }
   if (cur == 1) KSORT_HIP(hipMemcpyAsync(data, scratch, (size_t)n * sizeof(T), hipMemcpyDeviceToDevice, st));
