@@ -26,7 +26,7 @@ Prints ONE JSON line:
   cpu_baseline          the literal CPU oracle on the host, one thread
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
-                  [--copy-probe BYTES]
+                  [--copy-probe BYTES] [--exact-only]
 """
 from __future__ import annotations
 
@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--readings", type=int, default=50, help="sorts per size in the statistical-bound leg")
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only run device copies of this many bytes (counter calibration)")
+    p.add_argument("--exact-only", action="store_true",
+                   help="only run the literal-arrangement leg on the workload (profiling)")
     return p.parse_args()
 
 
@@ -308,6 +310,11 @@ def main() -> int:
         return 1
     if args.copy_probe:
         return copy_probe(args.copy_probe)
+    if args.exact_only:
+        w = synth.WORKLOADS[args.workload]
+        res = exact_leg(ksort, torch, synth.torch_fill(w["kind"], w["seed"], w["n"], torch.device("cuda:0")))
+        print(json.dumps({"exact": res, "workload": args.workload}), flush=True)
+        return 0 if res["verified"] else 3
     dev = torch.device("cuda:0")
     w = synth.WORKLOADS[args.workload]
     n = w["n"]
