@@ -40,6 +40,7 @@ constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kSpan = kThreads * kItems;  // positions per scan block
 constexpr int kScanThreads = 1024;        // the one workgroup that scans the block totals
+constexpr int kShort = 64;                // sort mode: sides of at most this many keys finish in one wave
 
 template <typename T>
 struct LevelArgs {
@@ -73,6 +74,10 @@ struct LevelArgs {
   const uint8_t* act;
   const uint8_t* act_prev;
   uint8_t* act_next;
+  // sort mode: sides of 2 .. kShort keys filed this level as (left, len);
+  // small_kernel makes all their remaining calls.  Null in level mode.
+  int2* small;
+  int32_t* nsmall;
 };
 
 // A block whose positions are all final at this level and the one before
@@ -324,10 +329,41 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
       if (a.first_pivot && k.left == 0 && k.right == a.n - 1) *a.first_pivot = k.i;
     }
     if (a.sort_mode) {
-      // Steps 5-6: [left, i-1] and [i+1, right] go on if they hold two or more keys
+      // Steps 5-6: [left, i-1] and [i+1, right] go on if they hold two or
+      // more keys; a side of at most kShort keys is filed for small_kernel
+      // (its first position files it) and its positions leave the levels
       int32_t nh = -1;
-      if (x < k.i && k.c >= 2) nh = (int32_t)k.left;
-      if (x > k.i && k.right - k.i >= 2) nh = (int32_t)(k.i + 1);
+      const int64_t cr = k.right - k.i;
+      bool file = false;
+      int2 entry{0, 0};
+      if (x < k.i && k.c >= 2) {
+        if (a.small && k.c <= kShort) {
+          file = x == k.left;
+          entry = make_int2((int32_t)k.left, (int32_t)k.c);
+        } else {
+          nh = (int32_t)k.left;
+        }
+      }
+      if (x > k.i && cr >= 2) {
+        if (a.small && cr <= kShort) {
+          file = x == k.i + 1;
+          entry = make_int2((int32_t)(k.i + 1), (int32_t)cr);
+        } else {
+          nh = (int32_t)(k.i + 1);
+        }
+      }
+      if (a.small) {
+        // one atomic per wave for the filed sides
+        const uint64_t fm = __ballot(file);
+        if (fm) {
+          const int lane = threadIdx.x & 63;
+          const int leader = __builtin_ctzll(fm);
+          int32_t base = 0;
+          if (lane == leader) base = atomicAdd(a.nsmall, (int32_t)__popcll(fm));
+          base = __shfl(base, leader);
+          if (file) a.small[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
+        }
+      }
       a.hd2[x] = nh;
       if (nh == x) a.ln2[x] = (int32_t)(x == k.left ? k.c : k.right - k.i);
       act += nh >= 0;
@@ -344,6 +380,100 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
   if (threadIdx.x == 0) {
     if (a.sort_mode && wsum[0]) atomicAdd(a.active, wsum[0]);
     if (a.ncalls && wsum[1]) atomicAdd(a.ncalls, wsum[1]);
+  }
+}
+
+// Bits a .. b of a 64-bit mask (empty when b < a); 0 <= a, b <= 63 or b = -1.
+__device__ __forceinline__ uint64_t bits_upto(int b) { return b < 0 ? 0ull : b >= 63 ? ~0ull : (2ull << b) - 1; }
+__device__ __forceinline__ uint64_t bit_range(int a, int b) { return b < a ? 0ull : bits_upto(b) & ~bits_upto(a - 1); }
+
+// Every remaining call on the sides filed this level (2 .. kShort keys
+// each), one wave per side and one key per lane, in nxt (the level's
+// output).  The wave runs the same closed form level by level on all
+// sub-segments of its side at once: a lane's sub-segment is (s, len), its key
+// is read from lane s, smaller-key counts come from the ballot of "smaller",
+// and the q and r lanes are filed by rank in LDS to find their partners.
+// The keys end where the recursion leaves them (ascending).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void small_kernel(LevelArgs<T> a) {
+  constexpr int NW = kThreads / 64;
+  __shared__ int32_t qs[NW][kShort + 1], rs[NW][kShort + 1];
+  __shared__ T vs[NW][kShort];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int32_t cnt = *a.nsmall;
+  unsigned long long ncall = 0;
+  for (int32_t e = (int32_t)blockIdx.x * NW + w; e < cnt; e += (int32_t)gridDim.x * NW) {
+    const int2 sg = a.small[e];
+    const int64_t gl = sg.x;
+    const int L = sg.y;
+    T v = lane < L ? a.nxt[gl + lane] : T(0);
+    int s = 0, len = lane < L ? L : 0;
+    for (;;) {
+      const bool act = len >= 2;
+      if (!__ballot(act)) break;
+      const int right = s + len - 1;
+      const T key = __shfl(v, act ? s : lane);
+      const bool lt = act && lane != s && !(key <= v);
+      const uint64_t ltm = __ballot(lt);
+      const int c = act ? __popcll(ltm & bit_range(s + 1, right)) : 0;
+      const int i = s + c;
+      const T vi1 = __shfl(v, act && i < right ? i + 1 : lane);
+      const int m = (act && i < right && key <= vi1) ? i + 1 : i;
+      const int lp = act && lane > s ? __popcll(ltm & bit_range(s + 1, lane)) : 0;
+      if (act && lane != s) {
+        if (lane <= m) {
+          if (!lt) qs[w][s + (lane - s) - lp] = lane;  // q, by rank in (s, m]
+        } else if (lt) {
+          rs[w][s + (c - lp + 1)] = lane;  // r, by rank from the right in (m, right]
+        }
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      int dest = lane;
+      if (act) {
+        const int kq = (lane - s) - lp;
+        if (lane == s)
+          dest = i;
+        else if (lane <= m)
+          dest = lt ? lane - 1 : (kq == 1 ? i + 1 : rs[w][s + kq - 1]);
+        else
+          dest = lt ? qs[w][s + (c - lp + 1)] - 1 : lane;
+      }
+      if (act && lane == s) {
+        if (a.calls) {
+          const unsigned long long j = atomicAdd(a.ncalls, 1ull);
+          if ((int64_t)j < a.calls_cap) {
+            a.calls[3 * j] = gl + s;
+            a.calls[3 * j + 1] = gl + right;
+            a.calls[3 * j + 2] = gl + i;
+          }
+        } else {
+          ++ncall;
+        }
+      }
+      vs[w][dest] = v;
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      v = vs[w][lane < kShort ? lane : 0];
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // all reads done before the next level's writes
+      if (act) {
+        if (lane < i) {
+          len = c >= 2 ? c : 0;
+        } else if (lane == i) {
+          len = 0;
+        } else {
+          s = i + 1;
+          len = right - i >= 2 ? right - i : 0;
+        }
+      }
+    }
+    if (lane < L) a.nxt[gl + lane] = v;
+  }
+  if (a.ncalls && !a.calls) {
+    __shared__ unsigned long long csum;
+    if (threadIdx.x == 0) csum = 0;
+    __syncthreads();
+    if (ncall) atomicAdd(&csum, ncall);
+    __syncthreads();
+    if (threadIdx.x == 0 && csum) atomicAdd(a.ncalls, csum);
   }
 }
 
@@ -431,6 +561,7 @@ static int launch_level(const LevelArgs<T>& a, hipStream_t st) {
   scan_apply<T><<<nb, kThreads, 0, st>>>(a);
   move_kernel<T><<<grid_for(a.n), kThreads, 0, st>>>(a);
   pair_kernel<T><<<grid_for(a.n), kThreads, 0, st>>>(a);
+  if (a.small) small_kernel<T><<<1024, kThreads, 0, st>>>(a);
   KSORT_HIP(hipGetLastError());
   return KSORT_OK;
 }
@@ -474,6 +605,7 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
   } hf{h_active};
   uint8_t* act_ring = nullptr;  // three levels of per-block activity flags
   if ((rc = B.take(&act_ring, (size_t)3 * a.nblocks))) return rc;
+  if ((rc = B.take(&a.small, (size_t)(n / 2 + 1))) || (rc = B.take(&a.nsmall, 1))) return rc;
   KSORT_HIP(hipMemsetAsync(act_ring, 1, (size_t)3 * a.nblocks, st));
   a.sort_mode = 1;
   a.calls = d_calls;
@@ -503,6 +635,7 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
       a.act_next = act_ring + (size_t)((level + 1) % 3) * a.nblocks;
       a.first_pivot = level == 0 ? d_first_pivot : nullptr;
       KSORT_HIP(hipMemsetAsync(a.active, 0, sizeof(unsigned long long), st));
+      KSORT_HIP(hipMemsetAsync(a.nsmall, 0, sizeof(int32_t), st));
       if ((rc = launch_level<T>(a, st))) return rc;
       cur ^= 1;
     }
