@@ -174,10 +174,16 @@ __global__ __launch_bounds__(kThreads) void scan_reduce(LevelArgs<T> a) {
   }
 }
 
-// One workgroup: the run carried into each scan block.
+// One workgroup: the run carried into each scan block.  It also clears the
+// level's counters (active positions, filed sides) before move_kernel and
+// pair_kernel use them.
 template <typename T>
 __global__ __launch_bounds__(kScanThreads) void scan_blocks(LevelArgs<T> a) {
   __shared__ int sf[kScanThreads], ss[kScanThreads];
+  if (threadIdx.x == 0) {
+    if (a.active) *a.active = 0;
+    if (a.nsmall) *a.nsmall = 0;
+  }
   const int nb = a.nblocks;
   const int per = (nb + kScanThreads - 1) / kScanThreads;
   const int b0 = threadIdx.x * per;
@@ -634,8 +640,6 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
       a.act_prev = act_ring + (size_t)((level + 2) % 3) * a.nblocks;
       a.act_next = act_ring + (size_t)((level + 1) % 3) * a.nblocks;
       a.first_pivot = level == 0 ? d_first_pivot : nullptr;
-      KSORT_HIP(hipMemsetAsync(a.active, 0, sizeof(unsigned long long), st));
-      KSORT_HIP(hipMemsetAsync(a.nsmall, 0, sizeof(int32_t), st));
       if ((rc = launch_level<T>(a, st))) return rc;
       cur ^= 1;
     }
