@@ -989,8 +989,12 @@ __global__ void clear_kernel(uint64_t* p, int64_t n) {
     p[j] = 0;
 }
 
-// Clears counters and flags before a run.
-__global__ void reset_kernel(StageCtr* ctr, Flags* flags) {
+// Clears the look-back words, counters and flags before a run (one kernel:
+// each boundary between kernels costs a few microseconds).
+__global__ void reset_kernel(StageCtr* ctr, Flags* flags, uint64_t* status, int64_t nwords) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nwords; j += (int64_t)gridDim.x * blockDim.x)
+    status[j] = 0;
+  if (blockIdx.x != 0) return;
   const int tid = threadIdx.x;
   if (tid < 3) {
     ctr[tid].nseg = 0;

@@ -336,15 +336,14 @@ OrderedLaunches::~OrderedLaunches() {
 int launch_reset(Workspace& ws) {
   const int64_t nwords = ws.caps.tiles;
   const int blocks = (int)std::min<int64_t>(1024, (nwords + 255) / 256);
-  hipLaunchKernelGGL(clear_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, ws.stream, ws.status, nwords);
-  KSORT_HIP(hipGetLastError());
   if (ws.stats) {
     const int64_t nk = 2 * (int64_t)ws.cap_stats;
     hipLaunchKernelGGL(clear_kernel, dim3((unsigned)std::min<int64_t>(256, (nk + 255) / 256)), dim3(256), 0, ws.stream,
                        (uint64_t*)ws.stage_keys, nk);
     KSORT_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, ws.stream, ws.ctr, ws.flags);
+  hipLaunchKernelGGL(reset_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, ws.stream, ws.ctr, ws.flags, ws.status,
+                     nwords);
   KSORT_HIP(hipGetLastError());
   return KSORT_OK;
 }
