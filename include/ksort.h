@@ -140,7 +140,7 @@ KSORT_API int ksort_partition_level(int dtype, const void *d_in, void *d_out, in
  *   Overlapping segments are rejected with KSORT_EINVAL (nothing is
  *   written); invalid segments are skipped as in ksort_partition_level.
  *   n < 2^31.  The segment arrays are read back to the host and the call
- *   synchronizes the stream; device scratch of about 3n * 4 + 2n *
+ *   synchronizes the stream; device scratch of about 25n + 2n *
  *   sizeof(key) bytes is allocated and freed inside the call.
  *
  * ksort_sort_exact: Steps 1-6 on d_data[0..n-1], in place, every partition
@@ -156,10 +156,11 @@ KSORT_API int ksort_partition_level(int dtype, const void *d_in, void *d_out, in
  *                   particular order.
  *   d_ncalls      : device int64, required with d_calls (else nullable):
  *                   the total number of calls (may exceed calls_cap).
- *   The call synchronizes the stream once per level (the level count is the
- *   recursion depth: about 2.5 log2 n on random keys, n on sorted input) and
- *   allocates about 5n * 4 + 4n * sizeof(key) bytes of device scratch for
- *   its duration.  n < 2^31.
+ *   The call synchronizes the stream once per eight levels (the level count
+ *   is the recursion depth down to sides of 64 keys, which one wave each
+ *   finishes: about 2 log2 n on random keys, about n on sorted input) and
+ *   allocates about 33n + 3n * sizeof(key) bytes of device scratch for its
+ *   duration.  n < 2^31.
  * Errors: KSORT_EINVAL (bad dtype, n < 0 or >= 2^31, null data with n > 0,
  * d_calls without d_ncalls), KSORT_ENOMEM, KSORT_EHIP, KSORT_EUNSUPPORTED. */
 KSORT_API int ksort_partition_level_exact(int dtype, const void *d_in, void *d_out, int64_t n,
