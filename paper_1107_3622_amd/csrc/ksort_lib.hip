@@ -65,6 +65,7 @@ const std::vector<Variant>& variants() {
       make_variant<double, 512, 16, 2048>(KSORT_F64),
       make_variant<double, 1024, 8, 2048>(KSORT_F64),
       make_variant<double, 512, 16, 1024>(KSORT_F64),
+      make_variant<float, 512, 32, 2048>(KSORT_F32),
       make_variant<float, 512, 24, 2048>(KSORT_F32),
       make_variant<float, 512, 16, 2048>(KSORT_F32),
       make_variant<float, 1024, 8, 2048>(KSORT_F32),
@@ -98,7 +99,10 @@ const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n) {
   }
   std::lock_guard<std::mutex> lk(g_default_mu);
   int j = g_default[dtype];
-  if (j < 0) j = variant_index(dtype, 512, 24, 2048);
+  // FP32 keys take 32 per thread: a tile then moves 64 KB, near the 96 KB
+  // of an FP64 tile of 24, which keeps the per-tile scan and look-back cost
+  // small against the data moved on large arrays
+  if (j < 0) j = dtype == KSORT_F64 ? variant_index(dtype, 512, 24, 2048) : variant_index(dtype, 512, 32, 2048);
   return &vs[j];
 }
 

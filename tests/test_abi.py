@@ -52,7 +52,8 @@ def test_host_only_calls(lib):
     for v in [(512, 24, 2048), (512, 16, 2048), (1024, 8, 2048), (512, 16, 1024)]:
         assert v in v64 and v in v32
     assert ksort.ksort_get_default(ksort.KSORT_F64) == (512, 24, 2048)
-    assert ksort.ksort_get_default(ksort.KSORT_F32) == (512, 24, 2048)
+    assert (512, 32, 2048) in v32
+    assert ksort.ksort_get_default(ksort.KSORT_F32) == (512, 32, 2048)
     assert lib.ksort_variants(7, None, 0) == -1
     # workspace: scratch of n keys plus descriptors, grows with n
     b1 = ksort.ksort_workspace_bytes(ksort.KSORT_F64, 1_000_000)
