@@ -29,6 +29,11 @@
  *   - The library keeps one scratch workspace per (device, stream) pair; calls
  *     on the same stream are serialised, calls on different streams run
  *     independently.
+ *   - No device wait is unbounded: a partition tile polls for its
+ *     predecessors' counts at most 2^22 times (seconds; the environment
+ *     variable KSORT_SPIN_LIMIT, a decimal count read whenever a level pass is
+ *     enqueued, overrides it) and then ends the pass, which the call reports
+ *     as KSORT_EINTERNAL.
  */
 #ifndef KSORT_H
 #define KSORT_H
@@ -57,7 +62,7 @@ extern "C" {
 #define KSORT_ECANCELLED (-7)  /* request cancelled */
 #define KSORT_ETIMEOUT (-8)    /* wait timed out */
 #define KSORT_ENOTFOUND (-9)   /* unknown server ticket */
-#define KSORT_EINTERNAL (-10)  /* internal capacity check failed (a library bug) */
+#define KSORT_EINTERNAL (-10)  /* a device check failed: a capacity or count (a library bug), or a look-back wait timed out */
 
 /* key types */
 #define KSORT_F64 0
@@ -84,7 +89,8 @@ typedef struct ksort_tuning {
  * descriptors, cached per (device, stream) and grown on demand.
  * Errors: KSORT_EINVAL (d_data NULL with n > 0, n < 0), KSORT_ENOMEM,
  * KSORT_EHIP, KSORT_EUNSUPPORTED.  On error the array content is unspecified
- * but remains a permutation of the input unless the error is KSORT_EHIP. */
+ * but remains a permutation of the input unless the error is KSORT_EHIP or
+ * KSORT_EINTERNAL. */
 KSORT_API int ksort_f64(double *d_data, int64_t n, void *stream);
 KSORT_API int ksort_f32(float *d_data, int64_t n, void *stream);
 

@@ -301,10 +301,14 @@ union StageSmem {
 
 constexpr int kLookBack = 4;
 
+// Returns -1 if a predecessor has not published after a.spin_limit polls
+// (the wait is bounded, so a lost or never-claimed predecessor ends the pass
+// with an error instead of holding the device).
 __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int32_t first_tile) {
   const int lane = lane_id();
   int64_t excl = 0;
   int32_t base = t - 1;
+  uint32_t polls = 0;
   for (;;) {
     uint64_t w[kLookBack];
     bool in_seg[kLookBack];
@@ -315,6 +319,7 @@ __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int3
       w[r] = in_seg[r] ? ld_agent(a.status + j) : 0;
     }
     // wait (per lane) until every watched predecessor has published
+    bool timed_out = false;
     for (;;) {
       bool ready = true;
 #pragma unroll
@@ -323,6 +328,10 @@ __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int3
         ready = ready && (!in_seg[r] || ok);
       }
       if (ready) break;
+      if (++polls > a.spin_limit) {
+        timed_out = true;
+        break;
+      }
       __builtin_amdgcn_s_sleep(1);
 #pragma unroll
       for (int r = 0; r < kLookBack; ++r) {
@@ -331,6 +340,7 @@ __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int3
         if (in_seg[r] && !ok) w[r] = ld_agent(a.status + j);
       }
     }
+    if (__ballot(timed_out)) return -1;
     // nearest predecessor with a full prefix: first slot with one, lowest
     // lane.  The predecessors nearer than it hold their own tile's count,
     // at most one tile's keys, so 64 of them sum in 32 bits.
@@ -529,7 +539,7 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
     int64_t xlt = 0;
     if (tidx > 0) {
       xlt = look_back(a, tk.t, tk.first_tile);
-      if (lane == 0) st_agent(a.status + tk.t, status_word(a.epoch, kFlagPre, (uint64_t)(xlt + tot_lt)));
+      if (lane == 0 && xlt >= 0) st_agent(a.status + tk.t, status_word(a.epoch, kFlagPre, (uint64_t)(xlt + tot_lt)));
     }
     if (lane == 0) {
       sm.xlt = xlt;
@@ -547,7 +557,7 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk, PartSmem<T, 
   const int64_t xge = o - (tidx > 0 ? 1 : 0) - xlt;
   const int64_t right = left + len - 1;
   if (xlt < 0 || xge < 0 || xlt + tot_lt > len - 1 || xge + tot_ge > len - 1) {
-    if (tid == 0) st_agent(&a.flags->overflow, 2);
+    if (tid == 0) st_agent(&a.flags->overflow, xlt == -1 ? 4 : 2);
     if (tid == BLOCK - 1) next->kind = kTaskNone;
     return;
   }

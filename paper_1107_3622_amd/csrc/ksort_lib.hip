@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -274,6 +275,21 @@ constexpr uint32_t kEpochSpan = (1u << 22) - 1;  // epochs 1 .. 2^22-1
 
 static uint32_t epoch_of(int stage) { return (uint32_t)(stage % kEpochSpan) + 1; }
 
+// Polls a look-back wait makes before its pass gives up with an error.  A
+// tile waits only for tiles that running workgroups hold, which publish within
+// microseconds; 2^22 polls take seconds.  KSORT_SPIN_LIMIT (a decimal count)
+// overrides it, read whenever a pass is enqueued (a captured graph keeps the
+// value it was captured with); tests use a tiny limit to force the error.
+static uint32_t spin_limit_setting() {
+  constexpr uint32_t kDefault = 1u << 22;
+  const char* s = getenv("KSORT_SPIN_LIMIT");
+  if (!s || !*s) return kDefault;
+  char* end = nullptr;
+  const unsigned long long v = strtoull(s, &end, 10);
+  if (*end != '\0' || v > 0xffffffffull) return kDefault;
+  return (uint32_t)v;
+}
+
 StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_out, int pivot_relative,
                      int emit_children) {
   StageArgs a;
@@ -303,6 +319,7 @@ StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_
   a.cutoff = v.cutoff;
   a.emit_children = emit_children;
   a.pivot_relative = pivot_relative;
+  a.spin_limit = spin_limit_setting();
   return a;
 }
 
@@ -578,6 +595,7 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       KSORT_HIP(hipStreamSynchronize(stream));
     }
     const Flags f = *ws.h_flags;
+    if (f.overflow == 4) return fail(KSORT_EINTERNAL, "a look-back wait timed out");
     if (f.overflow) return fail(KSORT_EINTERNAL, "device consistency check failed (code " + std::to_string(f.overflow) + ")");
     if (f.last_active < stage) {
       if (f.err) return fail(KSORT_EINVAL, "an array offset is outside [0, n_total] or decreasing");
@@ -660,6 +678,7 @@ static int run_level(int dtype, const void* d_in, void* d_out, int64_t n, const 
   if (rc) return rc;
   KSORT_HIP(hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, stream));
   KSORT_HIP(hipStreamSynchronize(stream));
+  if (ws.h_flags->overflow == 4) return fail(KSORT_EINTERNAL, "a look-back wait timed out");
   if (ws.h_flags->overflow) return fail(KSORT_EINTERNAL, "device consistency check failed");
   if (ws.h_flags->err) return fail(KSORT_EINVAL, "a segment is outside [0, n) or has len < 1");
   return KSORT_OK;

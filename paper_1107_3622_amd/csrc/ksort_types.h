@@ -40,7 +40,7 @@ struct StageCtr {
 struct Flags {
   int32_t last_active;  // highest stage index that has work
   int32_t err;          // invalid input segment seen by the init kernel
-  int32_t overflow;     // a device consistency check failed (code)
+  int32_t overflow;     // a device check failed: 1-3 capacity or count, 4 a look-back wait timed out
   int32_t pad;
 };
 
@@ -63,6 +63,7 @@ struct StageArgs {
   int32_t pivot_relative; // pivot reported as i - left (1) or as i (0)
   int32_t fin_run;        // finish tasks a stage with partition tiles runs; the rest wait a stage
   int32_t fin_half;       // finish lists: children below this index, carried tasks from it up
+  uint32_t spin_limit;    // polls of a look-back wait before the pass gives up (flag code 4)
 };
 
 // Arguments of the set-up kernel that turns input arrays (or, for a single

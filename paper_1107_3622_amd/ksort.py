@@ -153,6 +153,13 @@ def _check_keys(t) -> None:
         raise ValueError("keys must be a 1-D contiguous tensor")
 
 
+def _check_index_out(t, need: int, what: str) -> None:
+    """An int64 output array on the device with room for `need` entries."""
+    torch = _torch()
+    if t.dtype != torch.int64 or not t.is_cuda or not t.is_contiguous() or t.numel() < need:
+        raise ValueError(f"{what} must be a contiguous int64 device tensor of at least {need} entries")
+
+
 def _tuning(tune) -> Optional[Tuning]:
     if tune is None:
         return None
@@ -186,6 +193,8 @@ def ksort_sort_ex(t, first_pivot=None, tune=None, stream=None) -> None:
     """Sort in place; `first_pivot` (int64 device tensor of 1) receives the
     index at which the first partition left a[0]."""
     _check_keys(t)
+    if first_pivot is not None:
+        _check_index_out(first_pivot, 1, "first_pivot")
     fp = first_pivot.data_ptr() if first_pivot is not None else None
     tn = _tuning(tune)
     _check(load().ksort_sort_ex(_dtype_code(t), t.data_ptr(), t.numel(), fp, _ref(tn), _stream(stream)),
@@ -216,6 +225,8 @@ def ksort_partition_level(d_in, d_out, seg_left, seg_len, pivots=None, stream=No
         raise ValueError("seg_left and seg_len differ in length")
     if pivots is None:
         pivots = torch.empty(nseg, dtype=torch.int64, device=d_in.device)
+    else:
+        _check_index_out(pivots, nseg, "pivots")
     _check(load().ksort_partition_level(_dtype_code(d_in), d_in.data_ptr(), d_out.data_ptr(), d_in.numel(),
                                         seg_left.data_ptr(), seg_len.data_ptr(), nseg, pivots.data_ptr(),
                                         _stream(stream)), "ksort_partition_level")
@@ -239,6 +250,8 @@ def ksort_partition_level_exact(d_in, d_out, seg_left, seg_len, pivots=None, str
         raise ValueError("seg_left and seg_len differ in length")
     if pivots is None:
         pivots = torch.empty(nseg, dtype=torch.int64, device=d_in.device)
+    else:
+        _check_index_out(pivots, nseg, "pivots")
     _check(load().ksort_partition_level_exact(_dtype_code(d_in), d_in.data_ptr(), d_out.data_ptr(), d_in.numel(),
                                               seg_left.data_ptr(), seg_len.data_ptr(), nseg, pivots.data_ptr(),
                                               _stream(stream)), "ksort_partition_level_exact")
@@ -251,6 +264,8 @@ def ksort_sort_exact(t, calls_cap: int = 0, stream=None):
     (left, right, i) per call in no particular order, or None)."""
     torch = _torch()
     _check_keys(t)
+    if calls_cap < 0:
+        raise ValueError("calls_cap must be >= 0")
     fp = torch.empty(1, dtype=torch.int64, device=t.device)
     nc = torch.zeros(1, dtype=torch.int64, device=t.device)
     calls = torch.empty((max(calls_cap, 1), 3), dtype=torch.int64, device=t.device) if calls_cap > 0 else None
@@ -275,6 +290,8 @@ def ksort_segmented(t, offsets, first_pivots=None, tune=None, stream=None, want_
         raise ValueError("offsets needs at least one entry")
     if first_pivots is None and want_pivots:
         first_pivots = torch.empty(max(nseg, 1), dtype=torch.int64, device=t.device)
+    elif first_pivots is not None:
+        _check_index_out(first_pivots, nseg, "first_pivots")
     fp = first_pivots.data_ptr() if first_pivots is not None else None
     tn = _tuning(tune)
     _check(load().ksort_segmented(_dtype_code(t), t.data_ptr(), t.numel(), offsets.data_ptr(), nseg, fp,

@@ -115,3 +115,52 @@ def test_errors(ks):
         ks.ksort_sort_ex(t, tune=(256, 3, 2048))
     with pytest.raises(TypeError):
         ks.ksort_f32(t)
+    # output index arrays are checked before any device call: wrong type,
+    # host memory or too few entries are refused, and the keys are untouched
+    src = torch.arange(10, dtype=torch.float64, device="cuda").flip(0).contiguous()
+    t = src.clone()
+    for bad in (torch.zeros(1, dtype=torch.int64), torch.zeros(1, dtype=torch.int32, device="cuda"),
+                torch.zeros(0, dtype=torch.int64, device="cuda")):
+        with pytest.raises(ValueError):
+            ks.ksort_sort_ex(t, first_pivot=bad)
+    left = torch.tensor([0, 5], dtype=torch.int64, device="cuda")
+    length = torch.tensor([5, 5], dtype=torch.int64, device="cuda")
+    out = torch.zeros_like(t)
+    with pytest.raises(ValueError):
+        ks.ksort_partition_level(t, out, left, length, pivots=torch.zeros(1, dtype=torch.int64, device="cuda"))
+    with pytest.raises(ValueError):
+        ks.ksort_partition_level_exact(t, out, left, length, pivots=torch.zeros(2, dtype=torch.int64))
+    offs = torch.tensor([0, 4, 10], dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        ks.ksort_segmented(t, offs, first_pivots=torch.zeros(1, dtype=torch.int64, device="cuda"))
+    with pytest.raises(ValueError):
+        ks.ksort_sort_exact(t, calls_cap=-1)
+    assert torch.equal(t, src)
+
+
+def test_lookback_wait_is_bounded(ks, monkeypatch):
+    # A poll limit of 0 makes every tile that finds a predecessor's count not
+    # yet published end the pass at once: the call reports KSORT_EINTERNAL
+    # and every kernel exits normally.  With the limit restored the same
+    # workspace sorts correctly again.
+    torch = torch_dev()
+    src = synth.torch_fill("uniform_f64", 4, 7_000_000, "cuda")
+    ref = torch.sort(src)[0]
+    monkeypatch.setenv("KSORT_SPIN_LIMIT", "0")
+    raised = 0
+    for r in range(3):
+        note(f"spin limit 0, run {r}")
+        t = src.clone()
+        try:
+            ks.ksort_f64(t)
+        except ks.KsortError as e:
+            raised += 1
+            assert e.code == -10 and "timed out" in str(e)
+        else:
+            assert torch.equal(t, ref)
+    assert raised >= 1
+    monkeypatch.delenv("KSORT_SPIN_LIMIT")
+    note("spin limit restored")
+    t = src.clone()
+    ks.ksort_f64(t)
+    assert torch.equal(t, ref)
