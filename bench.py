@@ -27,6 +27,7 @@ Prints ONE JSON line:
                         leaving the paper's literal arrangement (the
                         sequential algorithm's calls, pivots and keys)
   cpu_baseline          the literal CPU oracle on the host, one thread
+  cpu_parallel          its task-parallel driver on up to 16 host cores
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
                   [--copy-probe BYTES] [--exact-only]
@@ -112,6 +113,29 @@ def cpu_baseline(workload: str, budget_s: float) -> dict:
             break
     mean = float(np.mean(times))
     return {"value": a.size / mean, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(times)} whole sorts of the same {a.size}-key array (mean {mean:.3f} s each)"}
+
+
+def cpu_parallel(workload: str, budget_s: float) -> dict:
+    """The oracle's task-parallel driver on the host's cores (at most 16):
+    the same literal calls, independent sub-arrays on different threads."""
+    import numpy as np
+
+    import oracle
+    import synth
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    a = synth.make(workload)
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        b = a.copy()
+        t0 = time.perf_counter()
+        oracle.sort_parallel_(b, threads)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start >= budget_s or len(times) >= 50:
+            break
+    mean = float(np.mean(times))
+    return {"value": a.size / mean, "unit": "keys/s", "cores": threads, "kind": "oracle, task-parallel",
             "sample": f"{len(times)} whole sorts of the same {a.size}-key array (mean {mean:.3f} s each)"}
 
 
@@ -331,13 +355,24 @@ def large_leg(ksort, torch, reps: int = 2) -> dict:
         ksort.ksort_profile_enable(False)
         recs = ksort.ksort_profile_read()
         ok = ok and bool(torch.equal(t, ref))
+        pass_bytes = [2 * kb * (r["live_keys"] + r["finish_keys"]) for r in recs]
         big = [r for r in recs if r["live_keys"] >= n // 2]
         big_bytes = sum(2 * kb * (r["live_keys"] + r["finish_keys"]) for r in big)
         big_ms = sum(r["ms"] for r in big)
         gbs = big_bytes / (big_ms * 1e-3) / 1e9 if big_ms > 0 else None
+        # every pass that moves at least 512 MB (twice the Infinity Cache):
+        # its own fraction of the HBM peak
+        fr = sorted(b / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                    for b, r in zip(pass_bytes, recs) if b >= 512 * 2**20 and r["ms"] > 0)
+        tot_ms = sum(r["ms"] for r in recs)
+        agg = sum(pass_bytes) / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else None
         out[name] = {"n": n, "ms": best * 1e3, "keys_per_s": n / best, "levels": len(recs),
                      "full_passes": len(big), "full_pass_avg_ms": big_ms / max(len(big), 1),
                      "full_passes_gbs": gbs, "full_passes_frac": gbs / HBM_PEAK_GBS if gbs else None,
+                     "passes_ge_512MB": {"count": len(fr), "frac_min": fr[0] if fr else None,
+                                         "frac_median": fr[len(fr) // 2] if fr else None,
+                                         "frac_max": fr[-1] if fr else None},
+                     "all_passes_gbs": agg, "all_passes_frac": agg / HBM_PEAK_GBS if agg else None,
                      "verified": ok}
         # a device copy of the same array: the read + write rate a plain
         # streaming kernel reaches on this GPU
@@ -350,6 +385,7 @@ def large_leg(ksort, torch, reps: int = 2) -> dict:
         torch.cuda.synchronize()
         copy_gbs = 5 * 2 * kb * n / (c0.elapsed_time(c1) * 1e-3) / 1e9
         out[name]["copy_gbs"] = copy_gbs
+        out[name]["full_passes_of_copy"] = gbs / copy_gbs if gbs else None
         del src, ref, t
         torch.cuda.empty_cache()
     return out
@@ -428,6 +464,19 @@ def main() -> int:
                (sum(r["ms"] for r in big) * 1e-3) / 1e9) if big else None
     traffic, traffic_src = stored_traffic()
 
+    # the read + write rate of a plain device copy of the same array (the
+    # practical ceiling of one pass at this size)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(20):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 20 * 2 * key_bytes * n / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del dst
+
     # correctness of the timed outputs: equal to the library sort of torch
     ref = torch.sort(src.clone())[0]
     ok = all(torch.equal(copies[args.warmup + k], ref) for k in range(2 * args.steps))
@@ -459,6 +508,8 @@ def main() -> int:
                      "launches": launches, "avg_launch_ms": tot_ms / max(launches, 1),
                      "alg_bytes_per_launch": tot_bytes / max(launches, 1),
                      "full_passes_gbs": big_gbs, "full_passes": len(big),
+                     "copy_gbs": copy_gbs,
+                     "full_passes_of_copy": big_gbs / copy_gbs if big_gbs else None,
                      "timing": "HIP events around every stage launch, second pass over fresh copies"},
         "levels_per_sort": launches / max(args.steps, 1),
         "partition_passes_per_key": sum(r["live_keys"] for r in recs) / (n * args.steps),
@@ -485,6 +536,8 @@ def main() -> int:
     if not args.no_cpu:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+        log("timing the task-parallel CPU oracle")
+        out["cpu_parallel"] = cpu_parallel(args.workload, args.cpu_seconds / 3)
     print(json.dumps(out), flush=True)
     return 0 if ok else 3
 

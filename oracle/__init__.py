@@ -23,7 +23,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libksort_oracle.so")
 SOURCES = [os.path.join(_HERE, "ksort_oracle.c")]
-CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC"]
+CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread"]
 
 _lib = None
 
@@ -73,6 +73,9 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         f.restype = ctypes.c_int
         f = getattr(lib, f"ksort_oracle_segmented_{sfx}")
         f.argtypes = [_p, _p, _i64, _p]
+        f.restype = ctypes.c_int
+        f = getattr(lib, f"ksort_oracle_sort_parallel_{sfx}")
+        f.argtypes = [_p, _i64, ctypes.c_int, ctypes.POINTER(_i64)]
         f.restype = ctypes.c_int
     return lib
 
@@ -130,6 +133,18 @@ def sort_(a: np.ndarray, trace_cap: int = 0, lib=None) -> dict:
     ntr = min(trace_cap, nc.value)
     return {"first_pivot": fp.value, "calls": nc.value, "comparisons": ncmp.value,
             "trace": [trace[t].as_dict() for t in range(ntr)]}
+
+
+def sort_parallel_(a: np.ndarray, threads: int, lib=None) -> int:
+    """Steps 1-6 in place with up to ``threads`` threads (independent
+    sub-arrays in parallel, every call literal); returns the first pivot."""
+    _check(a)
+    lib = lib or load()
+    fp = _i64()
+    rc = getattr(lib, f"ksort_oracle_sort_parallel_{_sfx(a)}")(a.ctypes.data, a.size, int(threads), ctypes.byref(fp))
+    if rc != 0:
+        raise MemoryError("oracle allocation or thread start failed")
+    return fp.value
 
 
 def sorted_copy(a: np.ndarray, lib=None) -> tuple[np.ndarray, int]:

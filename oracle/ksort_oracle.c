@@ -12,7 +12,9 @@
  * one-level arrangement, the exact mean comparison count of Quick sort, and
  * numpy's sort).
  */
+#include <pthread.h>
 #include <stdlib.h>
+#include <string.h>
 #include "ksort_oracle.h"
 
 #define KEY_T double

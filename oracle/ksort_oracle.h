@@ -57,6 +57,13 @@ int ksort_oracle_sort_f32(float *a, int64_t n, int64_t *first_pivot,
                           ksort_oracle_call *trace, int64_t trace_cap,
                           int64_t *ncalls, int64_t *ncomparisons);
 
+/* Steps 1-6 on a[0..n-1] with up to `threads` threads: the top of the
+ * recursion on the calling thread, then whole independent sub-arrays on the
+ * threads, each call the literal one.  The final array equals
+ * ksort_oracle_sort's; first_pivot as there.  Returns 0 or -2. */
+int ksort_oracle_sort_parallel_f64(double *a, int64_t n, int threads, int64_t *first_pivot);
+int ksort_oracle_sort_parallel_f32(float *a, int64_t n, int threads, int64_t *first_pivot);
+
 /* One partition call (Steps 1-4) on each segment [left[s], left[s]+len[s]-1]
  * (len[s] >= 1, segments disjoint); pivot[s] receives i.  Returns 0, or -1
  * on a segment with len < 1. */

@@ -146,6 +146,119 @@ int SFX(ksort_oracle_sort)(KEY_T *a, int64_t n, int64_t *first_pivot,
     return 0;
 }
 
+/* Steps 1-6 on a[0..n-1] by up to `threads` threads.  Every partition call
+ * is the literal one (ksort_oracle_partition); only sub-arrays that share no
+ * element run at the same time, so the final array equals the one-thread
+ * run's.  The threads share one stack of pending sub-arrays: a thread pops
+ * one, makes its call and pushes the sides of two or more elements (right
+ * side first, so the left one is popped first), or finishes a sub-array of
+ * at most `grain` elements alone with ksort_oracle_sort.  first_pivot as in
+ * ksort_oracle_sort.  Returns 0, or -2 when memory or a thread cannot be had. */
+struct SFX(oracle_pool) {
+    KEY_T *a;
+    int64_t n, grain;
+    pthread_mutex_t mu;
+    pthread_cond_t cv;
+    int64_t *stk;       /* (left, right) pairs */
+    int64_t top, cap;
+    int64_t pending;    /* sub-arrays pushed and not yet done */
+    int64_t *first_pivot;
+    int rc;
+};
+
+/* Pushes [left, right] (caller holds the lock); 0 or -2. */
+static int SFX(oracle_push)(struct SFX(oracle_pool) *q, int64_t left, int64_t right)
+{
+    if (q->top == q->cap) {
+        int64_t *ns = (int64_t *)realloc(q->stk, (size_t)q->cap * 4 * sizeof(int64_t));
+        if (!ns)
+            return -2;
+        q->stk = ns;
+        q->cap *= 2;
+    }
+    q->stk[2 * q->top] = left;
+    q->stk[2 * q->top + 1] = right;
+    q->top++;
+    q->pending++;
+    return 0;
+}
+
+static void *SFX(oracle_worker)(void *arg)
+{
+    struct SFX(oracle_pool) *q = (struct SFX(oracle_pool) *)arg;
+    pthread_mutex_lock(&q->mu);
+    for (;;) {
+        while (q->top == 0 && q->pending > 0 && q->rc == 0)
+            pthread_cond_wait(&q->cv, &q->mu);
+        if (q->top == 0 || q->rc != 0)
+            break;  /* everything is done, or a failure stops the run */
+        q->top--;
+        const int64_t left = q->stk[2 * q->top], right = q->stk[2 * q->top + 1];
+        pthread_mutex_unlock(&q->mu);
+        int rc = 0;
+        int64_t i = -1;
+        if (right - left + 1 <= q->grain)
+            rc = SFX(ksort_oracle_sort)(q->a + left, right - left + 1, NULL, NULL, 0, NULL, NULL);
+        else
+            i = SFX(ksort_oracle_partition)(q->a, left, right, NULL);
+        pthread_mutex_lock(&q->mu);
+        if (i >= 0) {
+            if (left == 0 && right == q->n - 1 && q->first_pivot)
+                *q->first_pivot = i;
+            /* Step-6 (R5), then Step-5 (R4) */
+            if (rc == 0 && right > i + 1)
+                rc = SFX(oracle_push)(q, i + 1, right);
+            if (rc == 0 && left < i - 1)
+                rc = SFX(oracle_push)(q, left, i - 1);
+        }
+        if (rc != 0)
+            q->rc = rc;
+        q->pending--;
+        pthread_cond_broadcast(&q->cv);
+    }
+    pthread_mutex_unlock(&q->mu);
+    return NULL;
+}
+
+int SFX(ksort_oracle_sort_parallel)(KEY_T *a, int64_t n, int threads, int64_t *first_pivot)
+{
+    if (threads < 1)
+        threads = 1;
+    int64_t grain = n / (64 * (int64_t)threads);
+    if (grain < 4096)
+        grain = 4096;
+    if (threads == 1 || n <= grain)
+        return SFX(ksort_oracle_sort)(a, n, first_pivot, NULL, 0, NULL, NULL);
+    struct SFX(oracle_pool) q;
+    memset(&q, 0, sizeof q);
+    q.a = a;
+    q.n = n;
+    q.grain = grain;
+    q.cap = 64;
+    q.first_pivot = first_pivot;
+    q.stk = (int64_t *)malloc((size_t)q.cap * 2 * sizeof(int64_t));
+    if (!q.stk)
+        return -2;
+    pthread_mutex_init(&q.mu, NULL);
+    pthread_cond_init(&q.cv, NULL);
+    (void)SFX(oracle_push)(&q, 0, n - 1);
+    pthread_t th[256];
+    const int nth = threads > 256 ? 256 : threads;
+    int started = 0;
+    for (int t = 1; t < nth; t++) {
+        if (pthread_create(&th[started], NULL, SFX(oracle_worker), &q) != 0)
+            break;
+        started++;
+    }
+    SFX(oracle_worker)(&q);  /* the calling thread works too */
+    for (int t = 0; t < started; t++)
+        pthread_join(th[t], NULL);
+    pthread_cond_destroy(&q.cv);
+    pthread_mutex_destroy(&q.mu);
+    free(q.stk);
+    return q.rc;
+}
+
 /* One application of Steps 1-4 to each listed segment. */
 int SFX(ksort_oracle_partition_level)(KEY_T *a, const int64_t *left,
                                       const int64_t *len, int64_t nseg,

@@ -77,3 +77,24 @@ def test_nan_goes_left(oracle_lib):
     a = np.array([0.5, np.nan, 0.7, 0.1])
     i, _ = oracle.partition_(a, 0, 3, lib=oracle_lib)
     assert i == 2 and np.isnan(a[:2]).sum() == 1
+
+
+@pytest.mark.parametrize("threads", [2, 5, 8])
+def test_parallel_driver_equals_one_thread(oracle_lib, threads):
+    # The task-parallel driver runs the same literal calls on sub-arrays that
+    # share no element; its array and first pivot must equal the one-thread
+    # run's (and numpy's order), bit for bit, including tie-heavy and
+    # ordered inputs and sizes around the task grain.
+    import synth
+    cases = [synth.uniform_f64(21, 700_000), np.floor(synth.uniform_f64(22, 300_000) * 16),
+             np.sort(synth.uniform_f64(23, 6000)), synth.uniform_f64(24, 4096),
+             synth.uniform_f64(25, 4097), synth.uniform_f64(26, 2), np.zeros(0),
+             synth.uniform_f64(27, 500_000).astype(np.float32)]
+    for a in cases:
+        b = a.copy()
+        info = oracle.sort_(b, lib=oracle_lib)
+        c = a.copy()
+        fp = oracle.sort_parallel_(c, threads, lib=oracle_lib)
+        assert np.array_equal(b.view(np.uint8), c.view(np.uint8))
+        assert np.array_equal(c, np.sort(a))
+        assert fp == info["first_pivot"]
