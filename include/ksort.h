@@ -228,11 +228,33 @@ KSORT_API int ksort_profile_enable(int on);
 KSORT_API int64_t ksort_profile_count(void);
 KSORT_API int64_t ksort_profile_read(ksort_level_record *out, int64_t cap);
 
-/* Bytes of device scratch a sort of n keys in nseg arrays needs (host only,
- * no device call). */
+/* Bytes of device scratch a sort (ksort_f64/f32, ksort_sort_ex with the
+ * default variant, ksort_segmented) or a one-level pass of n keys in nseg
+ * arrays or segments needs (host only, no device call).  0 for a bad dtype
+ * or a negative size. */
 KSORT_API size_t ksort_workspace_bytes(int dtype, int64_t n, int64_t nseg);
 
-/* Releases every cached workspace of the calling process (all devices). */
+/* ksort_set_workspace: the scratch of calls on `stream` of the current
+ * device comes from the caller's memory instead of the library's.
+ *   d_ws   : device memory, 256-byte aligned, of `bytes` bytes; owned by the
+ *            caller, who keeps it alive and leaves it alone until another
+ *            ksort_set_workspace on the same stream returns.  NULL hands the
+ *            stream back to memory the library allocates itself.
+ *   bytes  : size of d_ws, at least 4096.  Size it with ksort_workspace_bytes
+ *            for the largest call to come; a call that needs more fails
+ *            with KSORT_ENOMEM and allocates nothing.
+ *   stream : hipStream_t as void* (NULL = the null stream).
+ * Covers ksort_f64/f32, ksort_sort_ex, ksort_segmented and
+ * ksort_partition_level on that stream; the literal-arrangement calls and
+ * the server allocate their own.  The call waits for the stream's pending
+ * work, frees the library's memory of that stream and drops graphs captured
+ * for it.  Errors: KSORT_EINVAL (misaligned or smaller than 4096 bytes),
+ * KSORT_EHIP. */
+KSORT_API int ksort_set_workspace(void *d_ws, size_t bytes, void *stream);
+
+/* Releases every cached workspace of the calling process (all devices).
+ * Memory given with ksort_set_workspace is not freed (it is the caller's);
+ * the streams go back to library-owned memory. */
 KSORT_API int ksort_release_workspaces(void);
 
 /* ------------------------------------------------------------------------

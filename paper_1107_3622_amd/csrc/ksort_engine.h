@@ -83,10 +83,15 @@ struct Workspace {
   Flags* h_flags = nullptr;   // pinned readback
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<hipEvent_t> events; // pool for per-level timing (profiling mode)
+  void* user = nullptr;        // caller's device memory (ksort_set_workspace), or null
+  size_t user_bytes = 0;
   std::mutex mu;
   ~Workspace();
   // make room for a run; scratch_keys * key_bytes bytes of scratch
   int reserve(const Caps& c, size_t scratch_bytes_needed);
+  // frees the library's own memory and hands the workspace d (or, for null,
+  // memory the library allocates again); the caller holds mu
+  int use_memory(void* d, size_t bytes);
   uint32_t next_epoch();      // clears the look-back words when the tag wraps
 };
 

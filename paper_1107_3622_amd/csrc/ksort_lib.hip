@@ -187,49 +187,79 @@ static size_t arena_bytes_for(const Caps& c, int cap_stats) {
 Workspace::~Workspace() {
   for (auto e : events) (void)hipEventDestroy(e);
   if (capture) (void)hipStreamDestroy(capture);
-  if (arena) (void)hipFree(arena);
-  if (scratch) (void)hipFree(scratch);
+  if (!user) {
+    if (arena) (void)hipFree(arena);
+    if (scratch) (void)hipFree(scratch);
+  }
   if (h_flags) (void)hipHostFree(h_flags);
+}
+
+// Lays out the descriptor lists, counters, flags and look-back words in
+// `base` for caps `nc` and clears them.
+static int carve_arena(Workspace& w, void* base, const Caps& nc, size_t bytes) {
+  w.arena = base;
+  w.arena_bytes = bytes;
+  w.caps = nc;
+  w.cap_stats = (int)nc.stats;
+  char* p = (char*)base;
+  auto take = [&](size_t sz) {
+    char* r = p;
+    p += align256(sz);
+    return (void*)r;
+  };
+  w.ctr = (StageCtr*)take(3 * sizeof(StageCtr));
+  w.flags = (Flags*)take(sizeof(Flags));
+  for (int k = 0; k < 2; ++k) w.live[k] = (Seg*)take((size_t)nc.live * sizeof(Seg));
+  for (int k = 0; k < 2; ++k) w.tilemap[k] = (int32_t*)take((size_t)nc.tiles * sizeof(int32_t));
+  for (int k = 0; k < 2; ++k) w.fin[k] = (Seg*)take((size_t)2 * nc.fin * sizeof(Seg));
+  w.status = (uint64_t*)take((size_t)nc.tiles * sizeof(uint64_t));
+  w.stage_keys = (int64_t*)take((size_t)w.cap_stats * 2 * sizeof(int64_t));
+  w.pending = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
+  w.done_stage = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
+  KSORT_HIP(hipMemsetAsync(base, 0, bytes, w.stream));
+  w.epoch = 0;
+  return KSORT_OK;
 }
 
 int Workspace::reserve(const Caps& c, size_t scratch_need) {
   if (!h_flags) KSORT_HIP(hipHostMalloc((void**)&h_flags, sizeof(Flags), hipHostMallocDefault));
-  const bool fits = c.live <= caps.live && c.tiles <= caps.tiles && c.fin <= caps.fin && c.bufs <= caps.bufs &&
-                    c.stats <= caps.stats;
-  if (!arena || !fits) {
-    Caps nc;
+  const bool fits = arena && c.live <= caps.live && c.tiles <= caps.tiles && c.fin <= caps.fin &&
+                    c.bufs <= caps.bufs && c.stats <= caps.stats;
+  Caps nc = caps;
+  if (!fits) {
     nc.live = std::max(c.live, caps.live);
     nc.tiles = std::max(c.tiles, caps.tiles);
     nc.fin = std::max(c.fin, caps.fin);
     nc.bufs = std::max(c.bufs, caps.bufs);
     nc.stats = std::max(c.stats, caps.stats);
-    cap_stats = (int)nc.stats;
+  }
+  if (user) {
+    // the caller's memory: arena first, the scratch after it; nothing is
+    // allocated, a call that needs more fails
+    const size_t ab = arena_bytes_for(nc, (int)nc.stats);
+    const size_t need = align256(ab) + align256(std::max<size_t>(scratch_need, 1));
+    if (need > user_bytes)
+      return fail(KSORT_ENOMEM, "the workspace given to ksort_set_workspace holds " + std::to_string(user_bytes) +
+                                    " bytes; this call needs " + std::to_string(need));
+    if (!fits) {
+      int rc = carve_arena(*this, user, nc, ab);
+      if (rc) return rc;
+    }
+    scratch = (char*)user + align256(arena_bytes);
+    scratch_bytes = user_bytes - align256(arena_bytes);
+    return KSORT_OK;
+  }
+  if (!fits) {
     if (arena) {
       KSORT_HIP(hipStreamSynchronize(stream));
       KSORT_HIP(hipFree(arena));
       arena = nullptr;
     }
-    const size_t bytes = arena_bytes_for(nc, cap_stats);
-    KSORT_HIP(hipMalloc(&arena, bytes));
-    arena_bytes = bytes;
-    caps = nc;
-    char* p = (char*)arena;
-    auto take = [&](size_t sz) {
-      char* r = p;
-      p += align256(sz);
-      return (void*)r;
-    };
-    ctr = (StageCtr*)take(3 * sizeof(StageCtr));
-    flags = (Flags*)take(sizeof(Flags));
-    for (int k = 0; k < 2; ++k) live[k] = (Seg*)take((size_t)nc.live * sizeof(Seg));
-    for (int k = 0; k < 2; ++k) tilemap[k] = (int32_t*)take((size_t)nc.tiles * sizeof(int32_t));
-    for (int k = 0; k < 2; ++k) fin[k] = (Seg*)take((size_t)2 * nc.fin * sizeof(Seg));
-    status = (uint64_t*)take((size_t)nc.tiles * sizeof(uint64_t));
-    stage_keys = (int64_t*)take((size_t)cap_stats * 2 * sizeof(int64_t));
-    pending = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
-    done_stage = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
-    KSORT_HIP(hipMemsetAsync(arena, 0, bytes, stream));
-    epoch = 0;
+    const size_t bytes = arena_bytes_for(nc, (int)nc.stats);
+    void* base = nullptr;
+    KSORT_HIP(hipMalloc(&base, bytes));
+    int rc = carve_arena(*this, base, nc, bytes);
+    if (rc) return rc;
   }
   if (scratch_need > scratch_bytes) {
     if (scratch) {
@@ -241,6 +271,21 @@ int Workspace::reserve(const Caps& c, size_t scratch_need) {
     KSORT_HIP(hipMalloc(&scratch, scratch_need));
     scratch_bytes = scratch_need;
   }
+  return KSORT_OK;
+}
+
+int Workspace::use_memory(void* d, size_t bytes) {
+  KSORT_HIP(hipStreamSynchronize(stream));
+  if (!user) {
+    if (arena) KSORT_HIP(hipFree(arena));
+    if (scratch) KSORT_HIP(hipFree(scratch));
+  }
+  arena = nullptr;
+  scratch = nullptr;
+  arena_bytes = scratch_bytes = 0;
+  caps = Caps{};
+  user = d;
+  user_bytes = d ? bytes : 0;
   return KSORT_OK;
 }
 
@@ -765,10 +810,39 @@ int64_t ksort_profile_read(ksort_level_record* out, int64_t cap) {
 }
 
 size_t ksort_workspace_bytes(int dtype, int64_t n, int64_t nseg) {
-  const Variant* v = find_variant(dtype, nullptr);
+  const Variant* v = find_variant(dtype, nullptr, n);
   if (!v || n < 0 || nseg < 0) return 0;
-  const Caps c = caps_for(*v, n, nseg, false);
-  return arena_bytes_for(c, 256) + (size_t)n * v->key_bytes;
+  // the larger of the sort's and the one-level pass's lists
+  Caps c = caps_for(*v, n, nseg, false);
+  const Caps cl = caps_for(*v, n, nseg, true);
+  c.live = std::max(c.live, cl.live);
+  c.tiles = std::max(c.tiles, cl.tiles);
+  c.fin = std::max(c.fin, cl.fin);
+  c.bufs = std::max(c.bufs, cl.bufs);
+  c.stats = std::max(c.stats, cl.stats);
+  return align256(arena_bytes_for(c, (int)c.stats)) + align256((size_t)std::max<int64_t>(n, 1) * v->key_bytes);
+}
+
+int ksort_set_workspace(void* d_ws, size_t bytes, void* stream) {
+  if (d_ws && ((uintptr_t)d_ws % 256 != 0 || bytes < 4096))
+    return fail(KSORT_EINVAL, "the workspace must be 256-byte aligned and at least 4096 bytes");
+  int dev = 0;
+  KSORT_HIP(hipGetDevice(&dev));
+  Workspace& ws = *workspace_for(dev, (hipStream_t)stream);
+  std::lock_guard<std::mutex> lk(ws.mu);
+  {
+    // captured graphs hold pointers into the old memory
+    std::lock_guard<std::mutex> gl(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+      if (it->first.first == &ws) {
+        (void)hipGraphExecDestroy(it->second.exec);
+        it = g_graphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  return ws.use_memory(d_ws, bytes);
 }
 
 int ksort_release_workspaces(void) {

@@ -84,6 +84,7 @@ SIGNATURES = {
     "ksort_profile_count": (_i64, []),
     "ksort_profile_read": (_i64, [_p, _i64]),
     "ksort_workspace_bytes": (ctypes.c_size_t, [_int, _i64, _i64]),
+    "ksort_set_workspace": (_int, [_p, ctypes.c_size_t, _p]),
     "ksort_release_workspaces": (_int, []),
     "ksort_server_create": (_p, [ctypes.c_size_t, _int, _int]),
     "ksort_server_submit": (_int, [_p, _int, _p, _i64, ctypes.POINTER(ctypes.c_uint64)]),
@@ -341,8 +342,27 @@ def ksort_workspace_bytes(dtype: int, n: int, nseg: int = 1) -> int:
     return int(load().ksort_workspace_bytes(dtype, n, nseg))
 
 
+_user_ws: dict = {}  # stream handle -> tensor given to ksort_set_workspace (kept alive)
+
+
+def ksort_set_workspace(buf, stream=None) -> None:
+    """Scratch of calls on `stream` comes from `buf` (a contiguous uint8
+    device tensor), or from the library's own memory again for None."""
+    torch = _torch()
+    s = _stream(stream)
+    if buf is None:
+        _check(load().ksort_set_workspace(None, 0, s), "ksort_set_workspace")
+        _user_ws.pop(s, None)
+        return
+    if buf.dtype != torch.uint8 or not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("the workspace must be a contiguous uint8 device tensor")
+    _check(load().ksort_set_workspace(buf.data_ptr(), buf.numel(), s), "ksort_set_workspace")
+    _user_ws[s] = buf
+
+
 def ksort_release_workspaces() -> None:
     _check(load().ksort_release_workspaces(), "ksort_release_workspaces")
+    _user_ws.clear()
 
 
 def ksort_version() -> str:

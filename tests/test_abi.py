@@ -60,6 +60,10 @@ def test_host_only_calls(lib):
     b2 = ksort.ksort_workspace_bytes(ksort.KSORT_F64, 2_000_000)
     assert 8_000_000 < b1 < b2
     assert ksort.ksort_workspace_bytes(5, 10, 1) == 0
+    assert ksort.ksort_workspace_bytes(ksort.KSORT_F64, 0, 1) > 0
+    # caller memory: misaligned or too small is refused before any device call
+    assert lib.ksort_set_workspace(8, 1 << 20, None) == -1
+    assert lib.ksort_set_workspace(256, 1000, None) == -1
     # the literal-arrangement entry points check their arguments before any
     # device call
     assert lib.ksort_sort_exact(9, None, 0, None, None, 0, None, None) == -1
