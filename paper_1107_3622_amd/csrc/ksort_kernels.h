@@ -147,7 +147,11 @@ struct Task {
   Seg seg;
   int32_t kind;
   int32_t t;  // partition tiles: index into the stage's tile map (look-back slot)
+  int32_t bnext, bend;  // tickets [bnext, bend) claimed with this one and not yet taken
 };
+
+// Finish tickets claimed at once in a stage without partition tiles.
+constexpr int32_t kFinBatch = 32;
 
 __device__ __forceinline__ void load_seg(Seg* d, const KS_GLOBAL Seg* s) {
   d->left = s->left;
@@ -198,7 +202,26 @@ __device__ __forceinline__ int32_t fin_slot(const StageArgs& a, const Counts& cn
 __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out,
                                            int32_t first = -1) {
   const int par = a.stage & 1;
-  const int32_t t = first >= 0 ? first : add_agent(&cur->ticket, 1) + (int32_t)gridDim.x;
+  int32_t t;
+  if (first >= 0) {
+    t = first;
+    out->bnext = out->bend = 0;
+  } else if (out->bnext < out->bend) {
+    t = out->bnext++;
+  } else {
+    // In a stage without partition tiles nobody waits on a ticket's holder,
+    // so finish tickets are claimed in batches: one counter shared by the
+    // whole grid serves only a limited number of claims per microsecond.
+    // The batch shrinks as the tickets run out, to keep the stage's end even.
+    int32_t b = 1;
+    if (cn.ntiles == 0) {
+      const int32_t rest = cn.nwork - (ld_agent(&cur->ticket) + (int32_t)gridDim.x);
+      b = min(kFinBatch, max(1, rest / (4 * (int32_t)gridDim.x)));
+    }
+    t = add_agent(&cur->ticket, b) + (int32_t)gridDim.x;
+    out->bnext = t + 1;
+    out->bend = t + b;
+  }
   out->t = t;
   // Finish tasks take the first tickets: they never wait on anyone and take
   // longer than a tile, so starting them first keeps them off the end of the
@@ -224,7 +247,7 @@ __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, co
 // the block is free to load it, because every later tile of its segment waits
 // for its count in the look-back.
 __device__ __forceinline__ void claim_early(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out) {
-  if (ld_agent(&cur->ticket) + (int32_t)gridDim.x < cn.nwork - cn.ntiles)
+  if (out->bnext < out->bend || ld_agent(&cur->ticket) + (int32_t)gridDim.x < cn.nwork - cn.ntiles)
     fetch_task(a, cur, cn, out);
   else
     out->kind = kTaskUnclaimed;
