@@ -838,7 +838,6 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
       sm.outstanding = 0;
     }
     __syncthreads();
-    if (tid == BLOCK - 1) claim_early(a, cur, cn, next);
     // The top of the recursion runs on the whole workgroup: the segment
     // itself, then each of its sides of more than kBlockSide keys.  This cuts
     // the chain of large partitions that a single wave would otherwise do
@@ -869,6 +868,9 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
       }
     }
     __syncthreads();
+    // the successor is claimed now, when the queue holds at most four
+    // sub-segments for eight waves, so no barrier waits for the claim
+    if (tid == BLOCK - 1) claim_early(a, cur, cn, next);
     // Each wave takes sub-segments from the queue until none is outstanding;
     // after a partition it keeps the smaller side for itself and queues the
     // other.  Every branch of this loop is taken on a wave-uniform value
