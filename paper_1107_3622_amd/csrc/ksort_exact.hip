@@ -41,6 +41,8 @@ constexpr int kItems = 16;
 constexpr int kSpan = kThreads * kItems;  // positions per scan block
 constexpr int kScanThreads = 1024;        // the one workgroup that scans the block totals
 constexpr int kShort = 64;                // sort mode: sides of at most this many keys finish in one wave
+constexpr int kPairGrid = 4096;           // most workgroups of move_kernel and pair_kernel
+constexpr int kSmallGrid = 1024;          // workgroups of small_kernel
 
 template <typename T>
 struct LevelArgs {
@@ -66,6 +68,10 @@ struct LevelArgs {
   int64_t* calls;          // (left, right, i) per call, in no particular order
   int64_t calls_cap;
   unsigned long long* ncalls;
+  // sort mode without call records: per-workgroup call counts, one slot per
+  // workgroup of pair_kernel (kPairSlots) and of small_kernel after them;
+  // each slot belongs to one workgroup index, so plain adds suffice
+  unsigned long long* wcalls;
   int64_t* first_pivot;    // set by the call on [0, n-1] when not null
   unsigned long long* active;  // positions in segments of two or more keys next level
   // sort mode: per scan block, whether any of its positions is in a segment
@@ -295,97 +301,116 @@ __global__ __launch_bounds__(kThreads) void move_kernel(LevelArgs<T> a) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
-  unsigned long long act = 0, ncall = 0;
-  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < a.n; x += (int64_t)gridDim.x * kThreads) {
-    if (block_idle(a, x / kSpan)) continue;
-    const int32_t h = a.hd[x];
-    if (h < 0) {
-      if (a.sort_mode) a.hd2[x] = -1;
-      continue;
-    }
-    const Call<T> k = call_of(a, h);
-    const int64_t nq = (k.m - k.left) - a.ltp[k.m];  // keys >= key in (left, m]
-    const int64_t nr = k.c - a.ltp[k.m];             // smaller keys in (m, right]
-    const int64_t r = x - k.left;
-    // (the slots read here were filed by move_kernel in this level: the
-    // closed form has nr = nq or nq - 1; the range checks only keep a
-    // corrupted slot from writing outside the segment)
-    if (r >= 2 && r <= nq) {
-      const int64_t to = a.rpos[k.left + r - 1];
-      if (to > k.left && to <= k.right) a.nxt[to] = a.qkey[k.left + r];
-    }
-    if (r >= 1 && r <= nr) {
-      const int64_t to = (int64_t)a.qpos[k.left + r] - 1;
-      if (to >= k.left && to <= k.right) a.nxt[to] = a.rkey[k.left + r];
-    }
-    if (r == 0) {
-      // a call: with records wanted, each takes a slot (and so is counted);
-      // otherwise calls are only counted, one atomic per workgroup
-      if (a.calls) {
-        const unsigned long long j = atomicAdd(a.ncalls, 1ull);
-        if ((int64_t)j < a.calls_cap) {
-          a.calls[3 * j] = k.left;
-          a.calls[3 * j + 1] = k.right;
-          a.calls[3 * j + 2] = k.i;
-        }
+  constexpr int NW = kThreads / 64;
+  __shared__ int32_t fcnt[NW + 1];
+  unsigned long long ncall = 0;
+  bool any_active = false;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // Every thread of a workgroup runs the same iterations (the bound is on
+  // the workgroup's first position), so the barriers below are uniform.
+  for (int64_t base = (int64_t)blockIdx.x * kThreads; base < a.n; base += (int64_t)gridDim.x * kThreads) {
+    if (block_idle(a, base / kSpan)) continue;  // the same span block for the whole workgroup
+    const int64_t x = base + threadIdx.x;
+    bool file = false;
+    int2 entry{0, 0};
+    if (x < a.n) {
+      const int32_t h = a.hd[x];
+      if (h < 0) {
+        if (a.sort_mode) a.hd2[x] = -1;
       } else {
-        ++ncall;
+        const Call<T> k = call_of(a, h);
+        const int64_t nq = (k.m - k.left) - a.ltp[k.m];  // keys >= key in (left, m]
+        const int64_t nr = k.c - a.ltp[k.m];             // smaller keys in (m, right]
+        const int64_t r = x - k.left;
+        // (the slots read here were filed by move_kernel in this level: the
+        // closed form has nr = nq or nq - 1; the range checks only keep a
+        // corrupted slot from writing outside the segment)
+        if (r >= 2 && r <= nq) {
+          const int64_t to = a.rpos[k.left + r - 1];
+          if (to > k.left && to <= k.right) a.nxt[to] = a.qkey[k.left + r];
+        }
+        if (r >= 1 && r <= nr) {
+          const int64_t to = (int64_t)a.qpos[k.left + r] - 1;
+          if (to >= k.left && to <= k.right) a.nxt[to] = a.rkey[k.left + r];
+        }
+        if (r == 0) {
+          // a call: with records wanted, each takes a slot (and so is
+          // counted); otherwise it is counted in the workgroup's slot
+          if (a.calls) {
+            const unsigned long long j = atomicAdd(a.ncalls, 1ull);
+            if ((int64_t)j < a.calls_cap) {
+              a.calls[3 * j] = k.left;
+              a.calls[3 * j + 1] = k.right;
+              a.calls[3 * j + 2] = k.i;
+            }
+          } else {
+            ++ncall;
+          }
+          if (a.piv_at) a.piv_at[k.left] = (int32_t)k.i;
+          if (a.first_pivot && k.left == 0 && k.right == a.n - 1) *a.first_pivot = k.i;
+        }
+        if (a.sort_mode) {
+          // Steps 5-6: [left, i-1] and [i+1, right] go on if they hold two
+          // or more keys; a side of at most kShort keys is filed for
+          // small_kernel (its first position files it) and its positions
+          // leave the levels
+          int32_t nh = -1;
+          const int64_t cr = k.right - k.i;
+          if (x < k.i && k.c >= 2) {
+            if (a.small && k.c <= kShort) {
+              file = x == k.left;
+              entry = make_int2((int32_t)k.left, (int32_t)k.c);
+            } else {
+              nh = (int32_t)k.left;
+            }
+          }
+          if (x > k.i && cr >= 2) {
+            if (a.small && cr <= kShort) {
+              file = x == k.i + 1;
+              entry = make_int2((int32_t)(k.i + 1), (int32_t)cr);
+            } else {
+              nh = (int32_t)(k.i + 1);
+            }
+          }
+          a.hd2[x] = nh;
+          if (nh == x) a.ln2[x] = (int32_t)(x == k.left ? k.c : k.right - k.i);
+          if (nh >= 0) {
+            any_active = true;
+            if (a.act_next) a.act_next[x / kSpan] = 1;
+          }
+        }
       }
-      if (a.piv_at) a.piv_at[k.left] = (int32_t)k.i;
-      if (a.first_pivot && k.left == 0 && k.right == a.n - 1) *a.first_pivot = k.i;
     }
-    if (a.sort_mode) {
-      // Steps 5-6: [left, i-1] and [i+1, right] go on if they hold two or
-      // more keys; a side of at most kShort keys is filed for small_kernel
-      // (its first position files it) and its positions leave the levels
-      int32_t nh = -1;
-      const int64_t cr = k.right - k.i;
-      bool file = false;
-      int2 entry{0, 0};
-      if (x < k.i && k.c >= 2) {
-        if (a.small && k.c <= kShort) {
-          file = x == k.left;
-          entry = make_int2((int32_t)k.left, (int32_t)k.c);
-        } else {
-          nh = (int32_t)k.left;
+    if (a.small) {
+      // the workgroup's filed sides take one range of the list: one
+      // atomic per workgroup and iteration, not per wave
+      const uint64_t fm = __ballot(file);
+      if (lane == 0) fcnt[w] = (int32_t)__popcll(fm);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int32_t tot = 0;
+        for (int j = 0; j < NW; ++j) {
+          const int32_t c = fcnt[j];
+          fcnt[j] = tot;
+          tot += c;
         }
+        fcnt[NW] = tot ? atomicAdd(a.nsmall, tot) : 0;
       }
-      if (x > k.i && cr >= 2) {
-        if (a.small && cr <= kShort) {
-          file = x == k.i + 1;
-          entry = make_int2((int32_t)(k.i + 1), (int32_t)cr);
-        } else {
-          nh = (int32_t)(k.i + 1);
-        }
-      }
-      if (a.small) {
-        // one atomic per wave for the filed sides
-        const uint64_t fm = __ballot(file);
-        if (fm) {
-          const int lane = threadIdx.x & 63;
-          const int leader = __builtin_ctzll(fm);
-          int32_t base = 0;
-          if (lane == leader) base = atomicAdd(a.nsmall, (int32_t)__popcll(fm));
-          base = __shfl(base, leader);
-          if (file) a.small[base + __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
-        }
-      }
-      a.hd2[x] = nh;
-      if (nh == x) a.ln2[x] = (int32_t)(x == k.left ? k.c : k.right - k.i);
-      act += nh >= 0;
-      if (nh >= 0 && a.act_next) a.act_next[x / kSpan] = 1;
+      __syncthreads();
+      if (file) a.small[fcnt[NW] + fcnt[w] + __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
+      __syncthreads();  // fcnt is rewritten in the next iteration
     }
   }
-  // one global atomic per workgroup for each count
-  __shared__ unsigned long long wsum[2];
-  if (threadIdx.x < 2) wsum[threadIdx.x] = 0;
-  __syncthreads();
-  if (act) atomicAdd(&wsum[0], act);
-  if (ncall) atomicAdd(&wsum[1], ncall);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (a.sort_mode && wsum[0]) atomicAdd(a.active, wsum[0]);
-    if (a.ncalls && wsum[1]) atomicAdd(a.ncalls, wsum[1]);
+  // The next level runs while any position is in a segment of two or more
+  // keys: a flag, set with plain stores.  Calls are counted per workgroup.
+  if (a.sort_mode && __syncthreads_or(any_active) && threadIdx.x == 0) *a.active = 1ull;
+  if (a.wcalls) {
+    __shared__ unsigned long long csum;
+    if (threadIdx.x == 0) csum = 0;
+    __syncthreads();
+    if (ncall) atomicAdd(&csum, ncall);
+    __syncthreads();
+    if (threadIdx.x == 0 && csum) a.wcalls[blockIdx.x] += csum;
   }
 }
 
@@ -473,14 +498,28 @@ __global__ __launch_bounds__(kThreads) void small_kernel(LevelArgs<T> a) {
     }
     if (lane < L) a.nxt[gl + lane] = v;
   }
-  if (a.ncalls && !a.calls) {
+  if (a.wcalls) {
     __shared__ unsigned long long csum;
     if (threadIdx.x == 0) csum = 0;
     __syncthreads();
     if (ncall) atomicAdd(&csum, ncall);
     __syncthreads();
-    if (threadIdx.x == 0 && csum) atomicAdd(a.ncalls, csum);
+    if (threadIdx.x == 0 && csum) a.wcalls[kPairGrid + blockIdx.x] += csum;
   }
+}
+
+// Sums the per-workgroup call counts into *out (one workgroup).
+__global__ __launch_bounds__(kThreads) void sum_calls(const unsigned long long* w, int nslots, unsigned long long* out) {
+  __shared__ unsigned long long part[kThreads];
+  unsigned long long s = 0;
+  for (int j = threadIdx.x; j < nslots; j += kThreads) s += w[j];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int d = kThreads / 2; d > 0; d >>= 1) {
+    if (threadIdx.x < d) part[threadIdx.x] += part[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out += part[0];
 }
 
 // Whole array as one segment (sort mode, n >= 2).
@@ -515,7 +554,7 @@ __global__ __launch_bounds__(kThreads) void gather_pivots(const int32_t* piv_at,
 
 // ------------------------------------------------------------------ host
 
-static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, 4096)); }
+static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, kPairGrid)); }
 
 // Device buffers of one run, freed on scope exit.
 struct Buffers {
@@ -567,7 +606,7 @@ static int launch_level(const LevelArgs<T>& a, hipStream_t st) {
   scan_apply<T><<<nb, kThreads, 0, st>>>(a);
   move_kernel<T><<<grid_for(a.n), kThreads, 0, st>>>(a);
   pair_kernel<T><<<grid_for(a.n), kThreads, 0, st>>>(a);
-  if (a.small) small_kernel<T><<<1024, kThreads, 0, st>>>(a);
+  if (a.small) small_kernel<T><<<kSmallGrid, kThreads, 0, st>>>(a);
   KSORT_HIP(hipGetLastError());
   return KSORT_OK;
 }
@@ -617,6 +656,11 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
   a.calls = d_calls;
   a.calls_cap = d_calls ? calls_cap : 0;
   a.ncalls = (unsigned long long*)d_ncalls;
+  if (d_ncalls && !d_calls) {
+    // calls counted per workgroup, summed once at the end
+    if ((rc = B.take(&a.wcalls, (size_t)(kPairGrid + kSmallGrid)))) return rc;
+    KSORT_HIP(hipMemsetAsync(a.wcalls, 0, (size_t)(kPairGrid + kSmallGrid) * sizeof(unsigned long long), st));
+  }
   init_whole<<<grid_for(n), kThreads, 0, st>>>(H[0], Ln[0], n);
   KSORT_HIP(hipGetLastError());
   T* bufs[2] = {data, scratch};
@@ -648,6 +692,10 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
     if (*h_active == 0) break;
   }
   if (cur == 1) KSORT_HIP(hipMemcpyAsync(data, scratch, (size_t)n * sizeof(T), hipMemcpyDeviceToDevice, st));
+  if (a.wcalls) {
+    sum_calls<<<1, kThreads, 0, st>>>(a.wcalls, kPairGrid + kSmallGrid, a.ncalls);
+    KSORT_HIP(hipGetLastError());
+  }
   KSORT_HIP(hipStreamSynchronize(st));
   return KSORT_OK;
 }
