@@ -129,7 +129,7 @@ int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid);
 int stage_grid(const Variant& v, const DeviceInfo& di, const Caps& c);
 
 // Predicted number of level passes for n keys (used to size launch batches).
-int predict_stages(int64_t n, int cutoff);
+int predict_stages(int64_t n, int cutoff, int tile);
 
 // Whole sort of one packed buffer (single array when offsets == nullptr).
 int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64_t nseg,

@@ -160,9 +160,10 @@ Caps caps_for(const Variant& v, int64_t n, int64_t nseg, bool level_mode) {
     // live segments have more than `cutoff` keys and are disjoint
     c.live = n / (v.cutoff + 1) + 2;
     c.tiles = n / v.tile() + c.live + 2;
-    // stage 0 may hold every small input array; later stages at most two
-    // sides per live segment of the stage before
-    c.fin = std::max<int64_t>(nseg, 2 * c.live) + 2;
+    // stage 0 may hold every small input array; later stages at most
+    // kChainLists sides per live segment of the stage before (two, or more
+    // when a chain of one-tile segments is partitioned within the pass)
+    c.fin = std::max<int64_t>(nseg, (int64_t)kChainLists * c.live) + 2;
     // a sort of n keys takes at most about n level passes (ordered inputs)
     c.stats = std::min<int64_t>(n, 65536) + 64;
   }
@@ -440,10 +441,16 @@ int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid) 
   return KSORT_OK;
 }
 
-int predict_stages(int64_t n, int cutoff) {
+// Segments become one tile after about 2.6 log2(n / tile) levels on random
+// keys; from there a chain of one-tile segments runs within one pass and the
+// finish takes one more (measured: 12, 21 and 28 passes with work at 1e5, 1e6
+// and 7e6 keys).  Two spare passes cover most seeds; a short batch costs one
+// more round trip, an idle pass about 6 us.
+int predict_stages(int64_t n, int cutoff, int tile) {
   if (n <= cutoff) return 1;
-  const double r = std::log2((double)n / (double)cutoff);
-  return (int)std::ceil(2.7 * r) + 3;
+  if (n <= tile) return 4;
+  const double r = std::log2((double)n / (double)tile);
+  return (int)std::ceil(2.6 * r) + 6;
 }
 
 // ---------------------------------------------------------------- profiling
@@ -546,7 +553,8 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
   const int64_t call = next_call_id();
 
   int stage = 0;
-  int batch = predict_stages(n, v->cutoff);
+  int batch = predict_stages(n, v->cutoff, v->tile());
+  int more = 4;  // the batch after a short one; doubles up to 64
   bool graphed = false;
 
   if (use_graph && !prof) {
@@ -648,7 +656,8 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
     }
     // every level pass finishes at least one key per live segment
     if (stage > n + 64) return fail(KSORT_EINTERNAL, "level loop did not terminate");
-    batch = std::min(64, std::max(8, stage / 4));
+    batch = more;
+    more = std::min(64, 2 * more);
   }
 
   if (prof) {

@@ -2,7 +2,7 @@
 Sections 1 and 4, assumes i.i.d. keys; ordered inputs and heavy duplicates
 make every partition peel off a single key): sorted, reverse-sorted,
 all-equal and few-distinct inputs sort bit-exactly as the oracle sorts
-them, and the number of level passes is the depth that Steps 1-6 imply."""
+them, and the keys partitioned add up to what Steps 1-6 imply."""
 import numpy as np
 import pytest
 
@@ -38,13 +38,21 @@ def test_worst_case_inputs(kind):
     ksort.ksort_profile_enable(True)
     p = ksort.sort_(t)
     ksort.ksort_profile_enable(False)
+    recs = ksort.ksort_profile_read()
     # level passes that had work (the host's last batch of launches may run
     # past the last one; those find nothing to do)
-    levels = sum(1 for r in ksort.ksort_profile_read() if r["live_keys"] + r["finish_keys"] > 0)
+    levels = sum(1 for r in recs if r["live_keys"] + r["finish_keys"] > 0)
+    partitioned = sum(r["live_keys"] for r in recs)
+    finished = sum(r["finish_keys"] for r in recs)
     want, wp = oracle.sorted_copy(a)
     assert_bit_equal(to_host(t), want, kind)
     assert p == wp
     if kind in ("sorted", "reversed", "all_equal"):
         # every partition leaves one side empty and the other one key shorter:
-        # levels 0 .. N-CUTOFF-1 partition, the last one finishes CUTOFF keys
-        assert levels == N - CUTOFF + 1, levels
+        # segments of N, N-1, ..., CUTOFF+1 keys are partitioned, one each,
+        # and the last CUTOFF keys are finished in LDS.  A chain of one-tile
+        # segments runs within one pass, so the passes number at most one
+        # per partition plus the finish.
+        assert partitioned == sum(range(CUTOFF + 1, N + 1)), partitioned
+        assert finished == CUTOFF, finished
+        assert levels <= N - CUTOFF + 1, levels
