@@ -17,14 +17,19 @@
 //     from registers into the ping-pong buffer: smaller keys fill [left, i-1]
 //     upward, the others fill [i+1, right] downward, so i need not be known
 //     in advance.  The segment's last tile knows i, writes the key to its
-//     final place in the caller's array and emits the two sides.
+//     final place in the caller's array and emits the two sides.  When the
+//     segment had a single tile, the same workgroup may go on with one side
+//     of CUT+1 .. BLOCK*ITEMS keys in the same pass (a chain of one-tile
+//     segments), in passes where that cannot end the pass late.
 //   * finish tasks: a segment of at most CUT keys is loaded into LDS once
-//     and sorted there by the same rule: the block's waves take sub-segments
-//     from an LDS queue, partition one with wave ballots between two LDS
-//     buffers (more than 64 keys) or finish it in registers (64 keys or
-//     fewer), and write every key straight to its final place.
-// Both kinds of work come from one ticket counter per stage, partition tiles
-// first, so a persistent grid drains the stage without host involvement.
+//     and sorted there by the same rule: the workgroup partitions the top of
+//     the recursion, then its waves take sub-segments from an LDS queue and
+//     partition them with wave ballots between two LDS buffers; a
+//     sub-segment of at most kLeaf keys is placed by rank.  Every key is
+//     written straight to its final place.
+// Both kinds of work come from one ticket counter per stage, finish tasks
+// first, so a persistent grid drains the stage without host involvement; a
+// stage with no partition tiles hands out finish tickets in batches.
 #pragma once
 
 #include <hip/hip_runtime.h>
