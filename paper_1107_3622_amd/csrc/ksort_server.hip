@@ -151,6 +151,19 @@ static int lane_admit(ksort_server* s, Lane& L, Request& r) {
   return launch_init(L.ws, *L.v, ia, 1);
 }
 
+// After a failed device check the lane's lists may be incomplete; every
+// request on it has been failed.  Clearing its counters, flags, look-back
+// words and per-slot states lets it serve new requests.
+static int lane_recover(Lane& L) {
+  const size_t slots = L.slot_req.size();
+  KSORT_HIP(hipMemsetAsync(L.ws.done_stage, 0xff, slots * sizeof(int32_t), L.stream));
+  KSORT_HIP(hipMemsetAsync(L.ws.pending, 0, slots * sizeof(int32_t), L.stream));
+  int rc = launch_reset(L.ws);
+  if (rc) return rc;
+  KSORT_HIP(hipStreamSynchronize(L.stream));
+  return KSORT_OK;
+}
+
 // One tick of a lane: one stage over every admitted request, then the read
 // back of per-slot completion stages and pivots.
 static int lane_launch(ksort_server* s, Lane& L) {
@@ -239,6 +252,10 @@ static void server_loop(ksort_server* s) {
           L.slot_req[k] = 0;
           --L.active;
         }
+      }
+      if (lane_bad && rc == KSORT_OK) {
+        const int rr = lane_recover(L);
+        if (rr != KSORT_OK) rc = rr;
       }
     }
     if (rc != KSORT_OK) {

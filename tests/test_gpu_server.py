@@ -161,3 +161,42 @@ def test_poisson_stream_overlaps():
     overlaps = sum(1 for k in range(1, count) if infos[k]["t_admit_s"] < infos[k - 1]["t_done_s"])
     assert overlaps > 0
     assert st["completed"] == count and st["p99_latency_s"] > 0
+
+
+def test_lane_recovers_after_a_failed_device_check(monkeypatch):
+    # A look-back poll limit of 0 makes the partition passes of large
+    # requests end with a device error (every kernel still exits normally):
+    # those requests fail with KSORT_EINTERNAL.  The lane then clears its
+    # state, and the same server sorts new requests exactly as the oracle.
+    torch_dev()
+    from paper_1107_3622_amd import ksort
+    with ksort.Server(1 << 30, 16) as srv:
+        monkeypatch.setenv("KSORT_SPIN_LIMIT", "0")
+        note("server with spin limit 0")
+        tickets, keep = [], []
+        for r in range(4):
+            t = to_dev(request_keys(500 + r, 1_000_000, True))
+            tickets.append(srv.submit(t))
+            keep.append(t)
+        codes = [srv.wait(tk, 60.0) for tk in tickets]
+        for tk in tickets:
+            srv.release(tk)
+        assert all(c in (0, -10) for c in codes), codes
+        assert any(c == -10 for c in codes), codes
+        assert srv.stats()["failed"] >= 1
+        monkeypatch.delenv("KSORT_SPIN_LIMIT")
+        note("server after recovery")
+        reqs = [request_keys(600 + r, n, f64) for r, (n, f64) in enumerate(MIX)]
+        tickets, tensors = [], []
+        for a in reqs:
+            t = to_dev(a)
+            tickets.append(srv.submit(t))
+            tensors.append(t)
+        for tk in tickets:
+            assert srv.wait(tk, 60.0) == 0, srv.result(tk)
+        for a, t, tk in zip(reqs, tensors, tickets):
+            want, wfp = oracle.sorted_copy(a)
+            assert_bit_equal(to_host(t), want, f"request of {a.size} keys after recovery")
+            if a.size:
+                assert srv.result(tk)["first_pivot"] == wfp
+            srv.release(tk)
