@@ -213,8 +213,10 @@ KSORT_API int ksort_segmented(int dtype, void *d_packed, int64_t n_total,
 typedef struct ksort_level_record {
     int64_t call;         /* sequence number of the sorting call */
     int32_t dtype;
-    int32_t stage;        /* level index within the call (0 = whole arrays) */
-    int64_t live_keys;    /* keys partitioned in this pass */
+    int32_t stage;        /* pass index within the call (0 = whole arrays) */
+    int64_t live_keys;    /* keys partitioned in this pass, counted once per
+                             partition call (a chain of one-tile segments run
+                             within the pass counts each of its calls) */
     int64_t finish_keys;  /* keys sorted by the LDS finish in this pass */
     double ms;            /* pass duration from HIP events */
     int32_t block, items, cutoff, grid;
