@@ -86,6 +86,8 @@ static int variant_index(int dtype, int block, int items, int cutoff) {
   return -1;
 }
 
+static constexpr int64_t kSmallSortKeys = 3000000;
+
 const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n) {
   if (dtype != KSORT_F64 && dtype != KSORT_F32) return nullptr;
   const auto& vs = variants();
@@ -100,6 +102,12 @@ const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n) {
   }
   std::lock_guard<std::mutex> lk(g_default_mu);
   int j = g_default[dtype];
+  // Arrays below 3e6 keys (measured crossover between 2.5e6 and 4e6) sort
+  // faster with 16 keys per thread and a 1024-key LDS finish: more, shorter
+  // finish tasks at the levels that dominate small sorts (1e5: 0.29 against
+  // 0.32 ms, 1e6: 0.51 against 0.57, 2.5e6: 0.70 against 0.72; 4e6: 0.89
+  // against 0.84).  A default set by the caller or a tuned bucket wins.
+  if (j < 0 && n >= 0 && n < kSmallSortKeys) j = variant_index(dtype, 512, 16, 1024);
   // FP32 keys take 32 per thread: a tile then moves 64 KB, near the 96 KB
   // of an FP64 tile of 24, which keeps the per-tile scan and look-back cost
   // small against the data moved on large arrays

@@ -164,3 +164,21 @@ def test_lookback_wait_is_bounded(ks, monkeypatch):
     t = src.clone()
     ks.ksort_f64(t)
     assert torch.equal(t, ref)
+
+
+def test_small_arrays_take_the_small_variant(ks):
+    # Without a caller default or a tuned bucket, arrays below 3e6 keys run
+    # with 16 keys per thread and a 1024-key finish, larger ones with the
+    # default variant; both sort exactly.
+    torch = torch_dev()
+    for n, want in ((1_000_000, (512, 16, 1024)), (4_000_000, ks.ksort_get_default(ks.KSORT_F64))):
+        note(f"variant choice n={n}")
+        src = synth.torch_fill("uniform_f64", 7, n, "cuda")
+        t = src.clone()
+        ks.ksort_profile_read()
+        ks.ksort_profile_enable(True)
+        ks.ksort_f64(t)
+        ks.ksort_profile_enable(False)
+        recs = ks.ksort_profile_read()
+        assert {(r["block"], r["items"], r["cutoff"]) for r in recs} == {tuple(want)}
+        assert torch.equal(t, torch.sort(src)[0])

@@ -13,7 +13,6 @@ from gpu_util import assert_bit_equal, note, to_dev, to_host, torch_dev
 pytestmark = pytest.mark.gpu
 
 N = 20_000
-CUTOFF = 2048
 
 
 def inputs():
@@ -42,6 +41,7 @@ def test_worst_case_inputs(kind):
     # level passes that had work (the host's last batch of launches may run
     # past the last one; those find nothing to do)
     levels = sum(1 for r in recs if r["live_keys"] + r["finish_keys"] > 0)
+    cutoff = recs[0]["cutoff"]  # the LDS finish size of the variant that ran
     partitioned = sum(r["live_keys"] for r in recs)
     finished = sum(r["finish_keys"] for r in recs)
     want, wp = oracle.sorted_copy(a)
@@ -49,10 +49,10 @@ def test_worst_case_inputs(kind):
     assert p == wp
     if kind in ("sorted", "reversed", "all_equal"):
         # every partition leaves one side empty and the other one key shorter:
-        # segments of N, N-1, ..., CUTOFF+1 keys are partitioned, one each,
-        # and the last CUTOFF keys are finished in LDS.  A chain of one-tile
+        # segments of N, N-1, ..., cutoff+1 keys are partitioned, one each,
+        # and the last cutoff keys are finished in LDS.  A chain of one-tile
         # segments runs within one pass, so the passes number at most one
         # per partition plus the finish.
-        assert partitioned == sum(range(CUTOFF + 1, N + 1)), partitioned
-        assert finished == CUTOFF, finished
-        assert levels <= N - CUTOFF + 1, levels
+        assert partitioned == sum(range(cutoff + 1, N + 1)), partitioned
+        assert finished == cutoff, finished
+        assert levels <= N - cutoff + 1, levels
