@@ -202,7 +202,9 @@ KSORT_API int ksort_segmented(int dtype, void *d_packed, int64_t n_total,
  * ksort_variants: writes up to `cap` compiled variants for `dtype` to `out`
  *   (host array) and returns how many exist (or a negative error).
  * ksort_get_default / ksort_set_default: the variant used when `tune` is
- *   NULL, per key type (host struct).
+ *   NULL, per key type (host struct).  Unless a default was set or the size
+ *   was tuned, sorts of fewer than 3e6 keys use (512, 16, 1024) instead.
+ *   Servers and one-level passes always use the default.
  * ksort_autotune: times every variant on a seeded input of n keys on the
  *   current device and stores the fastest as the default for inputs of about
  *   that size; `out` (host, nullable) receives it.  Uses a temporary device
