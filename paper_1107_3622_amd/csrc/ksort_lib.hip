@@ -525,6 +525,22 @@ static int enqueue_prologue(Workspace& ws, const Variant& v, int dtype, void* d_
   return launch_init(ws, v, ia, nseg);
 }
 
+// Keys in the longest array of a packed batch (offsets read back once): the
+// recursion depth, and so the passes to launch, follow the longest array,
+// not the total.  Offsets the init kernel would reject count as empty.
+static int longest_array(const int64_t* d_offsets, int64_t nseg, int64_t n, hipStream_t stream, int64_t* out) {
+  std::vector<int64_t> h((size_t)nseg + 1);
+  KSORT_HIP(hipMemcpyAsync(h.data(), d_offsets, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+  KSORT_HIP(hipStreamSynchronize(stream));
+  int64_t m = 0;
+  for (int64_t u = 0; u < nseg; ++u) {
+    const int64_t len = h[(size_t)u + 1] - h[(size_t)u];
+    if (len > m && len <= n) m = len;
+  }
+  *out = m;
+  return KSORT_OK;
+}
+
 int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64_t nseg, int64_t* d_pivots,
              const ksort_tuning* tune, hipStream_t stream, bool use_graph) {
   if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
@@ -576,6 +592,11 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       it = g_graphs.end();
     }
     if (it == g_graphs.end()) {
+      if (d_offsets) {
+        int64_t longest = n;
+        if ((rc = longest_array(d_offsets, nseg, n, stream, &longest))) return rc;
+        batch = predict_stages(longest, v->cutoff, v->tile());
+      }
       // Record on a private stream (the caller's may be the legacy null
       // stream, which cannot be captured); the graph is launched on the
       // caller's stream.
@@ -616,6 +637,11 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
     stage = it->second.stages;
     graphed = true;
   } else {
+    if (d_offsets) {
+      int64_t longest = n;
+      if ((rc = longest_array(d_offsets, nseg, n, stream, &longest))) return rc;
+      batch = predict_stages(longest, v->cutoff, v->tile());
+    }
     rc = enqueue_prologue(ws, *v, dtype, d_data, n, d_offsets, nseg, d_pivots);
     if (rc) return rc;
   }
