@@ -664,15 +664,17 @@ __device__ void partition_tile(const StageArgs& a, const TaskU& tk0, PartSmem<T,
                                const Counts& cn, Task* next) {
   TaskU tk = tk0;
   int listed = 0;  // sides this chain has put on the lists
-  // Chains run where they cannot end the pass late: in a pass with fewer work
-  // items than workgroups (the tail of the recursion, where the next passes
-  // would otherwise hold little but these chains), or in a pass of four or
-  // more rounds of tiles, whose end a chain of a few tiles hardly moves.  In
-  // between, a chain started near the end of a pass of one or two rounds
-  // would delay it (measured: +1.5 % at 7e6 when chains run everywhere,
-  // -8.5 % with this rule; -6 % at 2^26 and -7 % at 2^28 either way).
+  // Chains run where they cannot end the pass late: in a pass with fewer
+  // tiles than a quarter of the workgroups (the tail of the recursion, where
+  // the next passes would otherwise hold little but these chains), or in a
+  // pass of four or more rounds of tiles, whose end a chain of a few tiles
+  // hardly moves.  In between, a chain started near the end of a pass of one
+  // or two rounds would delay it (measured: +1.5 % at 7e6 when chains run
+  // everywhere, -8 % with this rule; -6 % at 2^26 and -7 % at 2^28 either
+  // way; at 1e6 this tail bound gave 0.46 ms against 0.51 with "fewer work
+  // items than workgroups").
   const int32_t g = (int32_t)gridDim.x;
-  const bool chain_pass = cn.nwork < g || cn.ntiles >= 4 * g;
+  const bool chain_pass = cn.ntiles < g / 4 || cn.ntiles >= 4 * g;
   for (;;) {
     // a step that continues lists at most one side, the last one at most two
     const int r = partition_one<T, BLOCK, ITEMS>(a, tk, sm, next, chain_pass && listed + 3 <= kChainLists);
