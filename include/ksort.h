@@ -18,7 +18,9 @@
  *   - Keys are IEEE double (KSORT_F64) or float (KSORT_F32), compared in their
  *     own precision exactly as `key <= x`: ties go right; a NaN compares false
  *     and goes left.  The sorted order is unique (bit-exact with any correct
- *     sort) for inputs without NaN and without both +0.0 and -0.0.
+ *     sort) for inputs without NaN and without both +0.0 and -0.0.  With NaNs
+ *     the output is still a permutation of the input (every key is kept), in
+ *     an order that is not specified.
  *   - Sizes are element counts (int64_t).  n = 0 and n = 1 are valid no-ops.
  *   - Return value: KSORT_OK (0) or a negative KSORT_E* code; nothing is
  *     thrown across the ABI.  ksort_last_error() gives a thread-local detail
@@ -33,7 +35,19 @@
  *     predecessors' counts at most 2^22 times (seconds; the environment
  *     variable KSORT_SPIN_LIMIT, a decimal count read whenever a level pass is
  *     enqueued, overrides it) and then ends the pass, which the call reports
- *     as KSORT_EINTERNAL.
+ *     as KSORT_EINTERNAL; ksort_last_error() then names the pass, the waiting
+ *     tile and the predecessor it waited for.
+ *   - Look-back words are tagged with the pass number modulo 2^22 - 1 and
+ *     cleared when the tags wrap.  KSORT_EPOCH_SPAN (a decimal count in
+ *     [2, 2^22 - 1], read when a sort or a server starts) shortens the span,
+ *     so that tests reach the wrap in a few passes.
+ *   - Level passes of the plain and batched calls let workgroup b take work
+ *     ticket b without an atomic, which assumes the whole grid is dispatched
+ *     while its first workgroups wait.  Kernels of other code that keep part
+ *     of the device busy at the same time only delay such a pass (for as
+ *     long as they hold those slots; the bounded wait above ends it in an
+ *     error if that takes seconds).  The server's passes take every ticket
+ *     from a counter and do not depend on this.
  */
 #ifndef KSORT_H
 #define KSORT_H
@@ -292,7 +306,15 @@ KSORT_API int ksort_release_workspaces(void);
  *   request.
  * ksort_server_stats: aggregate counters and latency percentiles.
  * ksort_server_destroy: stops admitting, lets admitted requests finish,
- *   cancels queued ones, joins the thread and frees the server. */
+ *   cancels queued ones, joins the thread and frees the server.
+ * Request producers may run their own kernels on other streams while the
+ * server runs (the server's passes take every work ticket from a counter, so
+ * no pass waits for a workgroup that those kernels keep from starting).
+ * Each pass runs every finish task it lists (no finish work is deferred to a
+ * later pass).  A failed device check fails every request of that key
+ * type's lane with KSORT_EINTERNAL (ksort_server_wait then sets
+ * ksort_last_error() to the check's detail); the lane clears its state and
+ * goes on serving. */
 typedef struct ksort_server ksort_server;
 
 typedef struct ksort_request_info {

@@ -80,6 +80,8 @@ struct Workspace {
   int32_t* pending = nullptr;
   int32_t* done_stage = nullptr;
   uint32_t epoch = 0;         // last epoch used
+  int64_t epoch_span = (1 << 22) - 1;  // look-back tags of this run (see ksort_epoch.h)
+  uint64_t generation = 0;    // bumped whenever the arena or the scratch is laid out anew
   Flags* h_flags = nullptr;   // pinned readback
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<hipEvent_t> events; // pool for per-level timing (profiling mode)
@@ -101,6 +103,11 @@ void release_workspaces();
 // Arguments of one stage launch built from a workspace.
 StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_out, int pivot_relative,
                      int emit_children);
+
+// Error for a flag word read back after a batch of passes (KSORT_OK if the
+// device checks passed); a timed-out look-back wait names its pass, tile and
+// predecessor.
+int flags_error(const Flags& f);
 
 // Launch helpers (asynchronous on ws.stream).
 // Stage kernels of this library never run concurrently on one device (their
@@ -124,6 +131,7 @@ class OrderedLaunches {
 };
 
 int launch_reset(Workspace& ws);
+int launch_clear_status(Workspace& ws);  // the look-back words only
 int launch_init(Workspace& ws, const Variant& v, const InitArgs& ia, int64_t nblocks);
 int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid);
 int stage_grid(const Variant& v, const DeviceInfo& di, const Caps& c);

@@ -193,17 +193,31 @@ __device__ __forceinline__ int32_t fin_slot(const StageArgs& a, const Counts& cn
   return t < cn.ncar ? a.fin_half + t : t - cn.ncar;
 }
 
+// Tickets handed out by the stage's counter start at this value: the grid
+// size when every workgroup took its first ticket without the counter.
+__device__ __forceinline__ int32_t ticket_base(const StageArgs& a) {
+  return a.fixed_first ? (int32_t)gridDim.x : 0;
+}
+
 // Claims the next ticket of the stage and resolves it to a work item
 // (executed by one thread; the result goes to LDS for the block).
 //
-// Workgroup b takes ticket b as its first work item without an atomic (512
-// simultaneous claims on one counter would cost several microseconds per
-// stage); later tickets come from the stage's counter, offset by the grid
-// size.  A partition tile waits in its look-back for tiles with lower
-// tickets, so every ticket must belong to a workgroup that runs: the grid
-// never exceeds what the device holds at once, and the host orders all
-// stage-kernel launches of a device one after another, so no other kernel
-// that waits on its own workgroups can keep some of ours from starting.
+// A partition tile waits in its look-back for tiles with lower tickets, so
+// the holder of every lower ticket must be a workgroup that is running.
+// With tickets from the counter that holds by construction: a ticket is
+// claimed by a running workgroup, and the holder of the lowest unfinished
+// ticket never waits.  With fixed first tickets (a.fixed_first), workgroup b
+// takes ticket b without an atomic (512 simultaneous claims on one counter
+// cost several microseconds per stage) and later tickets come from the
+// counter offset by the grid size; then every workgroup of the grid must be
+// dispatched while earlier ones wait, which holds when nothing else occupies
+// the device: the grid never exceeds what the device holds at once, and the
+// host orders all stage-kernel launches of a device one after another.  A
+// kernel of other code that keeps part of the device busy delays the
+// dispatch of the remaining workgroups for as long as it or its successors
+// hold those slots, and tiles with counter tickets wait that long in their
+// look-back.  Where request producers run kernels at the same time by design
+// (the server), every ticket comes from the counter.
 __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out,
                                            int32_t first = -1) {
   const int par = a.stage & 1;
@@ -220,10 +234,10 @@ __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, co
     // The batch shrinks as the tickets run out, to keep the stage's end even.
     int32_t b = 1;
     if (cn.ntiles == 0) {
-      const int32_t rest = cn.nwork - (ld_agent(&cur->ticket) + (int32_t)gridDim.x);
+      const int32_t rest = cn.nwork - (ld_agent(&cur->ticket) + ticket_base(a));
       b = min(kFinBatch, max(1, rest / (4 * (int32_t)gridDim.x)));
     }
-    t = add_agent(&cur->ticket, b) + (int32_t)gridDim.x;
+    t = add_agent(&cur->ticket, b) + ticket_base(a);
     out->bnext = t + 1;
     out->bend = t + b;
   }
@@ -252,7 +266,7 @@ __device__ __forceinline__ void fetch_task(const StageArgs& a, StageCtr* cur, co
 // the block is free to load it, because every later tile of its segment waits
 // for its count in the look-back.
 __device__ __forceinline__ void claim_early(const StageArgs& a, StageCtr* cur, const Counts& cn, Task* out) {
-  if (out->bnext < out->bend || ld_agent(&cur->ticket) + (int32_t)gridDim.x < cn.nwork - cn.ntiles)
+  if (out->bnext < out->bend || ld_agent(&cur->ticket) + ticket_base(a) < cn.nwork - cn.ntiles)
     fetch_task(a, cur, cn, out);
   else
     out->kind = kTaskUnclaimed;
@@ -375,7 +389,28 @@ __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int3
         if (in_seg[r] && !ok) w[r] = ld_agent(a.status + j);
       }
     }
-    if (__ballot(timed_out)) return -1;
+    if (__ballot(timed_out)) {
+      // record the first predecessor still missing (the first failure of the
+      // pass wins), then give up
+      int32_t miss = -1;
+      uint64_t mw = 0;
+#pragma unroll
+      for (int r = kLookBack - 1; r >= 0; --r) {
+        const bool ok = (uint32_t)(w[r] >> 42) == a.epoch && ((w[r] >> 40) & 3) != 0;
+        if (in_seg[r] && !ok) {
+          miss = base - lane - kWave * r;
+          mw = w[r];
+        }
+      }
+      const uint64_t mm = __ballot(miss >= 0);
+      if (mm && lane == __builtin_ctzll(mm) && atomicCAS(&a.flags->overflow, 0, 4) == 0) {
+        a.flags->diag_stage = a.stage;
+        a.flags->diag_tile = t;
+        a.flags->diag_pred = miss;
+        a.flags->diag_word = mw;
+      }
+      return -1;
+    }
     // nearest predecessor with a full prefix: first slot with one, lowest
     // lane.  The predecessors nearer than it hold their own tile's count,
     // at most one tile's keys, so 64 of them sum in 32 bits.
@@ -707,6 +742,15 @@ constexpr int kBlockSide = 256;  // sides longer than this get a workgroup parti
 // no chain of dependent cross-lane steps.  The rank of the first key is the
 // segment's Step-4 pivot offset (no key before it can tie), written to
 // *pivot_slot when it is given.
+// Order used to place keys by rank when a leaf holds a NaN (outside the
+// bit-exact contract): numbers by value, every NaN after them.  Under it the
+// ranks are still a permutation of 0 .. L-1, so the output stays a
+// permutation of the input; without NaNs it is the plain `<`.
+template <typename T>
+__device__ __forceinline__ bool nan_last_less(T b, T v) {
+  return b < v || (v != v && b == b);
+}
+
 template <typename T, typename In>
 __device__ void wave_rank_sort(const In* in, T* out, int L, int64_t* pivot_slot, int64_t pivot_bias) {
   const int lane = lane_id();
@@ -714,16 +758,25 @@ __device__ void wave_rank_sort(const In* in, T* out, int L, int64_t* pivot_slot,
   asm volatile("" : "+v"(v));
   int rank = 0;
   int j = 0;
-  for (; j + 4 <= L; j += 4) {
+  if (__ballot(lane < L && v != v) == 0) {
+    for (; j + 4 <= L; j += 4) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const T b = lane_read(v, j + u);
-      rank += (b < v) | ((b <= v) & (j + u < lane));
+      for (int u = 0; u < 4; ++u) {
+        const T b = lane_read(v, j + u);
+        rank += (b < v) | ((b <= v) & (j + u < lane));
+      }
     }
-  }
-  for (; j < L; ++j) {
-    const T b = lane_read(v, j);
-    rank += (b < v) | ((b <= v) & (j < lane));
+    for (; j < L; ++j) {
+      const T b = lane_read(v, j);
+      rank += (b < v) | ((b <= v) & (j < lane));
+    }
+  } else {
+    // a NaN is present: the same placement under nan_last_less, equal
+    // (or both NaN) keys in lane order
+    for (; j < L; ++j) {
+      const T b = lane_read(v, j);
+      rank += (int)nan_last_less(b, v) | ((int)!nan_last_less(v, b) & (int)(j < lane));
+    }
   }
   if (lane < L) gst<T>(out, (uint32_t)(rank * sizeof(T)), v);
   if (pivot_slot && lane == 0) *pivot_slot = pivot_bias + rank;
@@ -745,25 +798,38 @@ __device__ void lds_rank_sort(const T* in, T* out, int L, int32_t* tie) {
   const int lane = lane_id();
   T v[K];
   int rank[K];
+  bool nan = false;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     v[k] = lane + kWave * k < L ? in[lane + kWave * k] : T(0);
     rank[k] = 0;
+    nan = nan || v[k] != v[k];
   }
   int j = 0;
-  for (; j + 8 <= L; j += 8) {
-    T b[8];
+  if (__ballot(nan) == 0) {
+    for (; j + 8 <= L; j += 8) {
+      T b[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) b[u] = in[j + u];
+      for (int u = 0; u < 8; ++u) b[u] = in[j + u];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
-      for (int k = 0; k < K; ++k) rank[k] += (int)(b[u] < v[k]);
-  }
-  for (; j < L; ++j) {
-    const T b = in[j];
+        for (int k = 0; k < K; ++k) rank[k] += (int)(b[u] < v[k]);
+    }
+    for (; j < L; ++j) {
+      const T b = in[j];
 #pragma unroll
-    for (int k = 0; k < K; ++k) rank[k] += (int)(b < v[k]);
+      for (int k = 0; k < K; ++k) rank[k] += (int)(b < v[k]);
+    }
+  } else {
+    // a NaN is present (outside the bit-exact contract): count under
+    // nan_last_less, so every NaN shares the count of all numbers and the
+    // tie placement below gives them the last places
+    for (; j < L; ++j) {
+      const T b = in[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) rank[k] += (int)nan_last_less(b, v[k]);
+    }
   }
   int sum = 0;
 #pragma unroll
@@ -1053,10 +1119,11 @@ __global__ __launch_bounds__(BLOCK) void stage_kernel(StageArgs a) {
     // are fewer, instead of a second round that would end this stage late.
     const int32_t ndef = nt > 0 && nf > a.fin_run ? min(nf - a.fin_run, a.cap_fin - a.fin_half) : 0;
     const Counts cn{nt, nt + nf - ndef, ncar};
+    next.bnext = next.bend = 0;
     if (ovf != 0)
       next.kind = kTaskNone;
     else
-      fetch_task(a, cur, cn, &next, (int32_t)blockIdx.x);
+      fetch_task(a, cur, cn, &next, a.fixed_first ? (int32_t)blockIdx.x : -1);
     s_counts[0] = cn.ntiles;
     s_counts[1] = cn.nwork;
     s_counts[2] = cn.ncar;
@@ -1123,6 +1190,10 @@ __global__ void reset_kernel(StageCtr* ctr, Flags* flags, uint64_t* status, int6
     flags->last_active = -1;
     flags->err = 0;
     flags->overflow = 0;
+    flags->diag_stage = -1;
+    flags->diag_tile = -1;
+    flags->diag_pred = -1;
+    flags->diag_word = 0;
   }
 }
 

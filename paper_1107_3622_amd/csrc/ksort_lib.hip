@@ -24,6 +24,7 @@
 
 #include "ksort.h"
 #include "ksort_engine.h"
+#include "ksort_epoch.h"
 #include "ksort_kernels.h"
 
 namespace ksort {
@@ -227,6 +228,7 @@ static int carve_arena(Workspace& w, void* base, const Caps& nc, size_t bytes) {
   w.done_stage = (int32_t*)take((size_t)nc.bufs * sizeof(int32_t));
   KSORT_HIP(hipMemsetAsync(base, 0, bytes, w.stream));
   w.epoch = 0;
+  ++w.generation;
   return KSORT_OK;
 }
 
@@ -254,7 +256,9 @@ int Workspace::reserve(const Caps& c, size_t scratch_need) {
       int rc = carve_arena(*this, user, nc, ab);
       if (rc) return rc;
     }
-    scratch = (char*)user + align256(arena_bytes);
+    char* const sc = (char*)user + align256(arena_bytes);
+    if (sc != scratch) ++generation;
+    scratch = sc;
     scratch_bytes = user_bytes - align256(arena_bytes);
     return KSORT_OK;
   }
@@ -279,6 +283,7 @@ int Workspace::reserve(const Caps& c, size_t scratch_need) {
     }
     KSORT_HIP(hipMalloc(&scratch, scratch_need));
     scratch_bytes = scratch_need;
+    ++generation;
   }
   return KSORT_OK;
 }
@@ -293,6 +298,7 @@ int Workspace::use_memory(void* d, size_t bytes) {
   scratch = nullptr;
   arena_bytes = scratch_bytes = 0;
   caps = Caps{};
+  ++generation;
   user = d;
   user_bytes = d ? bytes : 0;
   return KSORT_OK;
@@ -325,9 +331,6 @@ void release_workspaces() {
 #define KSORT_FIN_RUN(grid) (grid)
 #endif
 
-constexpr uint32_t kEpochSpan = (1u << 22) - 1;  // epochs 1 .. 2^22-1
-
-static uint32_t epoch_of(int stage) { return (uint32_t)(stage % kEpochSpan) + 1; }
 
 // Polls a look-back wait makes before its pass gives up with an error.  A
 // tile waits only for tiles that running workgroups hold, which publish within
@@ -366,15 +369,28 @@ StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_
   // caps.fin and the finish tasks carried over from it above.
   a.fin_half = (int32_t)ws.caps.fin;
   a.cap_fin = (int32_t)(2 * ws.caps.fin);
-  a.fin_run = 0x7fffffff;
+  a.fin_run = 0;  // launch_stage: one round of the grid
   a.cap_stats = ws.cap_stats;
   a.stage = stage;
-  a.epoch = epoch_of(stage);
+  a.epoch = epoch_of(stage, ws.epoch_span);
   a.cutoff = v.cutoff;
   a.emit_children = emit_children;
   a.pivot_relative = pivot_relative;
   a.spin_limit = spin_limit_setting();
+  a.fixed_first = 1;
   return a;
+}
+
+int flags_error(const Flags& f) {
+  if (f.overflow == 4) {
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "a look-back wait timed out (pass %d: tile %d waited for tile %d, whose word was 0x%016llx)",
+             f.diag_stage, f.diag_tile, f.diag_pred, (unsigned long long)f.diag_word);
+    return fail(KSORT_EINTERNAL, buf);
+  }
+  if (f.overflow) return fail(KSORT_EINTERNAL, "device consistency check failed (code " + std::to_string(f.overflow) + ")");
+  return KSORT_OK;
 }
 
 // ---------------------------------------------------------------- launch order
@@ -423,6 +439,14 @@ int launch_reset(Workspace& ws) {
   return KSORT_OK;
 }
 
+int launch_clear_status(Workspace& ws) {
+  const int64_t nwords = ws.caps.tiles;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (nwords + 255) / 256));
+  hipLaunchKernelGGL(clear_kernel, dim3(blocks), dim3(256), 0, ws.stream, ws.status, nwords);
+  KSORT_HIP(hipGetLastError());
+  return KSORT_OK;
+}
+
 int launch_init(Workspace& ws, const Variant& v, const InitArgs& ia, int64_t nblocks) {
   (void)v;
   if (nblocks <= 0) return KSORT_OK;
@@ -442,8 +466,9 @@ int stage_grid(const Variant& v, const DeviceInfo& di, const Caps& c) {
 
 int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid) {
   StageArgs args = a;
-  // one round of finish tasks on the grid in a stage that also partitions
-  args.fin_run = KSORT_FIN_RUN(grid);
+  // unless the caller chose otherwise, one round of finish tasks on the grid
+  // in a stage that also partitions
+  if (args.fin_run <= 0) args.fin_run = KSORT_FIN_RUN(grid);
   void* params[] = {&args};
   KSORT_HIP(hipLaunchKernel(v.stage, dim3(grid), dim3(v.block), params, 0, ws.stream));
   return KSORT_OK;
@@ -494,12 +519,29 @@ struct GraphKey {
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   int stages = 0;
-  void* arena = nullptr;    // workspace buffers the graph was recorded with
-  void* scratch = nullptr;
+  uint64_t generation = 0;  // layout of the workspace the graph was recorded with
+  int64_t epoch_span = 0;   // look-back tag span its passes used
+  uint64_t last_use = 0;
 };
 
+// Recorded graphs are kept per (workspace, arguments), at most kMaxGraphs of
+// them; the least recently used one is dropped first.  A graph holds the
+// pointers and list capacities of the workspace layout it was recorded
+// with, so it is used only while that layout (its generation) is current.
+constexpr size_t kMaxGraphs = 64;
 static std::mutex g_graph_mu;
 static std::map<std::pair<Workspace*, GraphKey>, GraphEntry> g_graphs;
+static uint64_t g_graph_clock = 0;
+
+static void evict_lru_graph() {
+  auto victim = g_graphs.end();
+  for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+    if (victim == g_graphs.end() || it->second.last_use < victim->second.last_use) victim = it;
+  if (victim != g_graphs.end()) {
+    (void)hipGraphExecDestroy(victim->second.exec);
+    g_graphs.erase(victim);
+  }
+}
 
 // ---------------------------------------------------------------- the sort
 
@@ -574,6 +616,7 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
   const int grid = stage_grid(*v, *di, ws.caps);
   const bool prof = profiling_on();
   ws.stats = prof;
+  ws.epoch_span = epoch_span_setting();
   const int64_t call = next_call_id();
 
   int stage = 0;
@@ -586,12 +629,13 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
     std::lock_guard<std::mutex> gl(g_graph_mu);
     auto gk = std::make_pair(&ws, key);
     auto it = g_graphs.find(gk);
-    if (it != g_graphs.end() && (it->second.arena != ws.arena || it->second.scratch != ws.scratch)) {
+    if (it != g_graphs.end() && it->second.generation != ws.generation) {
       (void)hipGraphExecDestroy(it->second.exec);
       g_graphs.erase(it);
       it = g_graphs.end();
     }
     if (it == g_graphs.end()) {
+      while (g_graphs.size() >= kMaxGraphs) evict_lru_graph();
       if (d_offsets) {
         int64_t longest = n;
         if ((rc = longest_array(d_offsets, nseg, n, stream, &longest))) return rc;
@@ -606,8 +650,10 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       const hipStream_t user = ws.stream;
       ws.stream = ws.capture;
       int crc = enqueue_prologue(ws, *v, dtype, d_data, n, d_offsets, nseg, d_pivots);
-      for (int s = 0; s < batch && crc == KSORT_OK; ++s)
-        crc = launch_stage(ws, *v, stage_args(ws, *v, s, d_pivots, 1, 1), grid);
+      for (int s = 0; s < batch && crc == KSORT_OK; ++s) {
+        if (epoch_wraps_before(s, ws.epoch_span)) crc = launch_clear_status(ws);
+        if (crc == KSORT_OK) crc = launch_stage(ws, *v, stage_args(ws, *v, s, d_pivots, 1, 1), grid);
+      }
       if (crc == KSORT_OK) {
         hipError_t e = hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, ws.capture);
         if (e != hipSuccess) crc = hip_fail(e, "hipMemcpyAsync(flags)");
@@ -624,10 +670,12 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
       ge.stages = batch;
-      ge.arena = ws.arena;
-      ge.scratch = ws.scratch;
+      ge.generation = ws.generation;
+      ge.epoch_span = ws.epoch_span;
       it = g_graphs.emplace(gk, ge).first;
     }
+    it->second.last_use = ++g_graph_clock;
+    ws.epoch_span = it->second.epoch_span;  // the passes after the graph continue its tags
     {
       OrderedLaunches order(dev, stream);
       if (order.status()) return order.status();
@@ -656,10 +704,9 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       OrderedLaunches order(dev, stream);
       if (order.status()) return order.status();
       for (int b = 0; b < batch; ++b, ++stage) {
-        if (stage > 0 && stage % (int)kEpochSpan == 0) {
-          const int64_t nwords = ws.caps.tiles;
-          hipLaunchKernelGGL(clear_kernel, dim3(256), dim3(256), 0, ws.stream, ws.status, nwords);
-          KSORT_HIP(hipGetLastError());
+        if (epoch_wraps_before(stage, ws.epoch_span)) {
+          rc = launch_clear_status(ws);
+          if (rc) return rc;
         }
         if (prof) {
           while (ws.events.size() < nev + 2) {
@@ -682,8 +729,7 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
       KSORT_HIP(hipStreamSynchronize(stream));
     }
     const Flags f = *ws.h_flags;
-    if (f.overflow == 4) return fail(KSORT_EINTERNAL, "a look-back wait timed out");
-    if (f.overflow) return fail(KSORT_EINTERNAL, "device consistency check failed (code " + std::to_string(f.overflow) + ")");
+    if ((rc = flags_error(f))) return rc;
     if (f.last_active < stage) {
       if (f.err) return fail(KSORT_EINVAL, "an array offset is outside [0, n_total] or decreasing");
       break;
@@ -766,8 +812,7 @@ static int run_level(int dtype, const void* d_in, void* d_out, int64_t n, const 
   if (rc) return rc;
   KSORT_HIP(hipMemcpyAsync(ws.h_flags, ws.flags, sizeof(Flags), hipMemcpyDeviceToHost, stream));
   KSORT_HIP(hipStreamSynchronize(stream));
-  if (ws.h_flags->overflow == 4) return fail(KSORT_EINTERNAL, "a look-back wait timed out");
-  if (ws.h_flags->overflow) return fail(KSORT_EINTERNAL, "device consistency check failed");
+  if ((rc = flags_error(*ws.h_flags))) return rc;
   if (ws.h_flags->err) return fail(KSORT_EINVAL, "a segment is outside [0, n) or has len < 1");
   return KSORT_OK;
 }

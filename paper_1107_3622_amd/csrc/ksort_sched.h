@@ -42,7 +42,7 @@ struct Request {
   int levels = 0;
   int slot = -1;             // buffer-pair slot while admitted
   size_t scratch_off = 0;    // offset of its scratch in the arena
-  int admit_stage = 0;
+  int64_t admit_stage = 0;  // server pass at which it joined its lane
 };
 
 // First-fit allocator of [0, size) with coalescing of free ranges.

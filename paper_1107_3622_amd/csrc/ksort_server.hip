@@ -25,6 +25,7 @@
 
 #include "ksort.h"
 #include "ksort_engine.h"
+#include "ksort_epoch.h"
 #include "ksort_sched.h"
 
 namespace ksort {
@@ -39,7 +40,7 @@ struct Lane {
   const Variant* v = nullptr;
   hipStream_t stream = nullptr;
   Workspace ws;
-  int stage = 0;
+  int64_t stage = 0;              // passes launched on this lane (64-bit: a busy lane never wraps it)
   int grid = 1;
   int active = 0;                 // admitted, unfinished requests
   std::vector<uint64_t> slot_req; // slot -> request id (0 = free)
@@ -65,6 +66,7 @@ struct ksort_server {
   bool stop = false;
   int thread_error = 0;
   std::string thread_error_msg;
+  std::string last_failure;  // detail of the latest failed request (device check)
   double busy_since = -1;
   ksort_server(size_t b, int mi) : max_inflight(mi), budget(b), sched(b, mi, 1u << 20), scratch_alloc(b / 2) {}
 };
@@ -88,6 +90,7 @@ static int lane_init(ksort_server* s, Lane& L, int dtype) {
   L.ws.device = s->device;
   L.ws.stream = L.stream;
   L.ws.cap_stats = 1;
+  L.ws.epoch_span = epoch_span_setting();
   const int64_t n_eff = (int64_t)(s->budget / (2 * L.v->key_bytes));
   Caps c = caps_for(*L.v, n_eff, s->max_inflight, false);
   c.live += s->max_inflight;
@@ -124,11 +127,23 @@ static void lane_free(Lane& L) {
   L.stream = nullptr;
 }
 
+// Pass s of a lane runs as kernel pass kernel_stage(s) with the look-back
+// tag of s itself (ksort_epoch.h).  A request's completion is seen after the
+// tick in which it completes, so its level count follows from the host's s.
 static StageArgs server_args(Lane& L) {
-  StageArgs a = stage_args(L.ws, *L.v, L.stage, L.d_pivot, 1, 1);
+  StageArgs a = stage_args(L.ws, *L.v, kernel_stage(L.stage), L.d_pivot, 1, 1);
+  a.epoch = epoch_of(L.stage, L.ws.epoch_span);
   a.pending = L.ws.pending;
   a.done_stage = L.ws.done_stage;
   a.stage_keys = nullptr;
+  // Request producers run kernels while the server's passes run, so a
+  // workgroup of a pass may wait for slots they hold: every work ticket comes
+  // from the counter, so no tile waits for a workgroup that has not started.
+  a.fixed_first = 0;
+  // Every finish task runs in the pass that lists it: a busy server always
+  // has partition tiles, and deferring finish work to a pass without tiles
+  // would hold requests back for as long as new ones keep arriving.
+  a.fin_run = 0x7fffffff;
   return a;
 }
 
@@ -167,8 +182,11 @@ static int lane_recover(Lane& L) {
 // One tick of a lane: one stage over every admitted request, then the read
 // back of per-slot completion stages and pivots.
 static int lane_launch(ksort_server* s, Lane& L) {
-  if (L.stage > 0 && L.stage % (int)((1u << 22) - 1) == 0) {
-    int rc = launch_reset(L.ws);  // look-back tags wrap: clear them
+  if (epoch_wraps_before(L.stage, L.ws.epoch_span)) {
+    // The look-back tags wrap: clear the words and nothing else.  The stage
+    // counters, lists and per-slot counts hold the work of the requests in
+    // flight and go on unchanged.
+    int rc = launch_clear_status(L.ws);
     if (rc) return rc;
   }
   {
@@ -236,6 +254,10 @@ static void server_loop(ksort_server* s) {
       Lane& L = s->lanes[d];
       if (!launched[d] && rc == KSORT_OK) continue;
       const bool lane_bad = rc != KSORT_OK || (launched[d] && L.h_flags->overflow);
+      if (lane_bad) {
+        if (rc == KSORT_OK) (void)flags_error(*L.h_flags);
+        s->last_failure = ksort_last_error();
+      }
       for (size_t k = 0; k < L.slot_req.size(); ++k) {
         const uint64_t id = L.slot_req[k];
         if (!id) continue;
@@ -243,12 +265,13 @@ static void server_loop(ksort_server* s) {
         if (!r) continue;
         if (lane_bad) {
           s->scratch_alloc.release(r->scratch_off, r->scratch_bytes);
-          s->sched.complete(id, rc != KSORT_OK ? rc : KSORT_EINTERNAL, t2, -1, L.stage - r->admit_stage);
+          s->sched.complete(id, rc != KSORT_OK ? rc : KSORT_EINTERNAL, t2, -1, (int)(L.stage - r->admit_stage));
           L.slot_req[k] = 0;
           --L.active;
         } else if (L.h_done[k] >= 0) {
           s->scratch_alloc.release(r->scratch_off, r->scratch_bytes);
-          s->sched.complete(id, kReqDone, t2, L.h_pivot[k], L.h_done[k] - r->admit_stage + 1);
+          // completed in the pass just read back, pass L.stage - 1
+          s->sched.complete(id, kReqDone, t2, L.h_pivot[k], (int)(L.stage - r->admit_stage));
           L.slot_req[k] = 0;
           --L.active;
         }
@@ -352,7 +375,8 @@ int ksort_server_wait(ksort_server* s, uint64_t ticket, double timeout_s) {
   const Request* r = s->sched.find(ticket);
   if (!r) return fail(KSORT_ENOTFOUND, "unknown ticket");
   if (r->state == kReqDone) return KSORT_OK;
-  return fail(r->state, "request failed or was cancelled");
+  if (r->state == KSORT_ECANCELLED) return fail(r->state, "request cancelled");
+  return fail(r->state, "request failed: " + (s->last_failure.empty() ? std::string("no detail") : s->last_failure));
 }
 
 int ksort_server_cancel(ksort_server* s, uint64_t ticket) {

@@ -41,7 +41,10 @@ struct Flags {
   int32_t last_active;  // highest stage index that has work
   int32_t err;          // invalid input segment seen by the init kernel
   int32_t overflow;     // a device check failed: 1-3 capacity or count, 4 a look-back wait timed out
-  int32_t pad;
+  int32_t diag_stage;   // code 4: the pass whose wait timed out (first failure only)
+  int32_t diag_tile;    // code 4: ticket index of the waiting tile in that pass's tile map
+  int32_t diag_pred;    // code 4: ticket index of the predecessor it waited for
+  uint64_t diag_word;   // code 4: that predecessor's look-back word when the wait gave up
 };
 
 struct StageArgs {
@@ -64,6 +67,7 @@ struct StageArgs {
   int32_t fin_run;        // finish tasks a stage with partition tiles runs; the rest wait a stage
   int32_t fin_half;       // finish lists: children below this index, carried tasks from it up
   uint32_t spin_limit;    // polls of a look-back wait before the pass gives up (flag code 4)
+  int32_t fixed_first;    // 1: workgroup b takes ticket b first (no counter); 0: every ticket from the counter
 };
 
 // Arguments of the set-up kernel that turns input arrays (or, for a single

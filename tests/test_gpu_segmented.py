@@ -81,3 +81,31 @@ def test_bad_offsets_rejected():
         note(f"bad offsets {offs}")
         with pytest.raises(ksort.KsortError):
             ksort.ksort_segmented(t, to_dev(np.array(offs, dtype=np.int64)))
+
+
+def test_epoch_wrap_segmented(monkeypatch):
+    # the recorded graph clears the look-back words at each wrap of the tags
+    torch_dev()
+    monkeypatch.setenv("KSORT_EPOCH_SPAN", "3")
+    keys, offs = synth.batched(31, 32, 257, 32, 65536)
+    check(keys, offs, "batched 257 arrays, tags wrap every 3 passes")
+
+
+def test_c3_full_batch():
+    # The batched workload itself: 4096 arrays, lengths log-uniform in
+    # [32, 65536] (seed 9), keys from seed 10; every array and first pivot
+    # against the oracle, recorded graph then replay.
+    torch = torch_dev()
+    from paper_1107_3622_amd import ksort
+    keys, offs = synth.batched(9, 10, 4096, 32, 65536)
+    want = keys.copy()
+    wfp = oracle.segmented_(want, offs)
+    src = to_dev(keys)
+    d_off = to_dev(offs)
+    for r in range(2):
+        note(f"c3 batch of 4096 arrays, {keys.size} keys, run {r}")
+        t = src.clone()
+        fp = torch.empty(offs.size - 1, dtype=torch.int64, device="cuda")
+        ksort.ksort_segmented(t, d_off, first_pivots=fp)
+        assert_bit_equal(to_host(t), want, f"c3 run {r}")
+        assert np.array_equal(to_host(fp), wfp), f"c3 run {r}: first pivots"

@@ -182,3 +182,34 @@ def test_small_arrays_take_the_small_variant(ks):
         recs = ks.ksort_profile_read()
         assert {(r["block"], r["items"], r["cutoff"]) for r in recs} == {tuple(want)}
         assert torch.equal(t, torch.sort(src)[0])
+
+
+def test_epoch_wrap_plain(ks, monkeypatch):
+    # Look-back tags that wrap every 3 passes (KSORT_EPOCH_SPAN, read when a
+    # sort starts): the words are cleared at each wrap, and the sorts stay
+    # bit-exact, also on ordered input, where the passes number in thousands.
+    monkeypatch.setenv("KSORT_EPOCH_SPAN", "3")
+    check(ks, synth.uniform_f64(41, 1_000_000), "tags wrap every 3 passes, f64")
+    check(ks, synth.uniform_f32(42, 250_001), "tags wrap every 3 passes, f32")
+    check(ks, np.sort(synth.uniform_f64(43, 12_000)), "tags wrap every 3 passes, sorted input")
+
+
+def bits_multiset(a: np.ndarray) -> np.ndarray:
+    u = a.view(np.uint64 if a.dtype == np.float64 else np.uint32)
+    return np.sort(u)
+
+
+@pytest.mark.parametrize("n", [40, 100, 1500, 50_000, 600_000])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_nan_inputs_stay_a_permutation(ks, n, dt):
+    # NaN is outside the bit-exact contract (a NaN compares false and goes
+    # left), but the output must still hold every input key: the leaves that
+    # place keys by rank order NaNs after the numbers.
+    rng = np.random.default_rng(n)
+    for frac in (0.01, 0.3, 1.0):
+        a = rng.random(n).astype(dt)
+        a[rng.random(n) < frac] = np.nan
+        a[0] = np.nan if frac > 0.2 else a[0]  # a NaN as the first key
+        note(f"NaN fraction {frac} n={n} {np.dtype(dt).name}")
+        got, _ = gpu_sort(ks, a)
+        assert np.array_equal(bits_multiset(got), bits_multiset(a)), f"n={n} frac={frac}: keys lost or duplicated"
