@@ -2,7 +2,6 @@
 and key types, admitted while others run, each sorted bit-exactly as the
 oracle sorts it alone; the same result alone and in the mix; admission by
 memory budget; cancellation of queued requests."""
-import os
 import time
 
 import numpy as np
@@ -232,9 +231,6 @@ def test_epoch_wrap_keeps_requests_in_flight(monkeypatch):
 C4_REQUESTS = 160
 
 
-@pytest.mark.skipif(os.environ.get("KSORT_RUN_C4") != "1",
-                    reason="the full serving stream stalled on the device before the server took every work "
-                           "ticket from the counter; kept off until that fix has run once (KSORT_RUN_C4=1)")
 def test_c4_scale_stream_with_concurrent_producer():
     """The serving workload's shape: requests of 1e3 .. 1e7 keys (log-uniform),
     70 % FP64, 128 in flight under a 64 GiB budget, each request's keys drawn
