@@ -14,8 +14,10 @@ Prints ONE JSON line:
   batched               4096 arrays (log-uniform lengths in [32, 65536]) in
                         one segmented call vs 4096 plain calls vs one plain
                         sort of the same key count
-  serve                 a seeded Poisson stream of requests through the sort
-                        server: p50/p99 latency and keys/s
+  serve                 the serving workload: a seeded Poisson stream of 20,000
+                        requests of 1e3 .. 1e7 keys through the sort server
+                        (p50/p99 latency and keys/s beside the plain path),
+                        then a saturation run
   statbound             the paper's run-time model (Section 3) fitted to
                         this sort over Table 1's sizes
   worst_case            sorted, reversed, all-equal and four-valued inputs:
@@ -200,40 +202,178 @@ def batched_leg(ksort, torch) -> dict:
             "verified": bool(ok)}
 
 
-def serve_leg(ksort, torch) -> dict:
-    """A seeded Poisson stream through the sort server, submitted at its
-    arrival times while earlier requests are on the device: 120 requests,
-    sizes log-uniform in [1e3, 1e5], 70 % FP64, 2000 arrivals/s, 32 in
-    flight under a 1 GiB budget.  Inputs are drawn on the device before
-    the stream starts.  (The full stream of 20,000 requests of up to 1e7 keys
-    under 64 GiB stalled on the device and is not run; see the design
-    notes.)"""
+def _bits_checksum(torch, t):
+    """Order-independent checksum of a key array's bit patterns: two wrapping
+    int64 sums of mixed bit patterns (a permutation keeps both)."""
+    v = t.view(torch.int64) if t.dtype == torch.float64 else t.view(torch.int32).to(torch.int64)
+    a = (v * 0x2545F4914F6CDD1D).sum()
+    b = (v ^ (v >> 29)).sum()
+    return torch.stack([a, b])
+
+
+def _plain_rate(ksort, torch, sizes, kinds, count: int) -> float:
+    """Keys/s of the plain single-array path over the first `count` requests
+    of the stream's size mix, one call per request, inputs resident."""
     import synth
-    count = 120
-    sizes, is_f64, arrivals = synth.serve_requests(count, 12, 13, 11, 1_000, 100_000, 0.7, 2000.0)
-    reqs = [synth.torch_fill("uniform_f64" if f else "uniform_f32", synth.REQUEST_SEED_BASE + r, int(n), "cuda")
-            for r, (n, f) in enumerate(zip(sizes, is_f64))]
-    refs = [torch.sort(t)[0] for t in reqs]
-    torch.cuda.synchronize()
-    with ksort.Server(1 << 30, 32) as srv:
+    total_keys, total_s = 0, 0.0
+    for r in range(count):
+        t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
+        fn = ksort.ksort_f64 if t.dtype == torch.float64 else ksort.ksort_f32
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tks = []
-        for t, at in zip(reqs, arrivals):
-            dt = at - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tks.append(srv.submit(t))
-        rcs = [srv.wait(tk, 60.0) for tk in tks]
+        fn(t)
+        total_s += time.perf_counter() - t0
+        total_keys += int(sizes[r])
+        del t
+    return total_keys / total_s
+
+
+def _run_stream(ksort, torch, sizes, kinds, arrivals, budget: int, inflight: int, pre_drawn=None,
+                keep=()) -> dict:
+    """Submits request r at arrivals[r] (keys drawn on a producer stream just
+    before, unless pre_drawn holds them); a checker thread waits for the
+    requests in order, checks each output is sorted and has its input's
+    checksum, and drops it (except the indices in `keep`)."""
+    import threading
+
+    import synth
+    count = len(sizes)
+    prod = torch.cuda.Stream()
+    chk = torch.cuda.Stream()
+    tickets = [None] * count
+    sums = [None] * count
+    kept = {}
+    bad = []
+    codes = [None] * count
+    ready = threading.Semaphore(0)
+    tensors = [None] * count
+
+    def checker():
+        with torch.cuda.stream(chk):
+            for r in range(count):
+                ready.acquire()
+                codes[r] = srv.wait(tickets[r], 300.0)
+                t = tensors[r]
+                if codes[r] == 0:
+                    ok = bool((t[1:] >= t[:-1]).all().item()) if t.numel() > 1 else True
+                    ok = ok and torch.equal(_bits_checksum(torch, t), sums[r])
+                    if not ok:
+                        bad.append(r)
+                if r in keep:
+                    kept[r] = t
+                tensors[r] = None
+                srv.release(tickets[r])
+
+    with ksort.Server(budget, inflight) as srv:
+        th = threading.Thread(target=checker)
+        th.start()
+        t0 = time.perf_counter()
+        for r in range(count):
+            if pre_drawn is None:
+                dt = arrivals[r] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                with torch.cuda.stream(prod):
+                    t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
+                    sums[r] = _bits_checksum(torch, t)
+                prod.synchronize()
+            else:
+                t, sums[r] = pre_drawn[r]
+            tensors[r] = t
+            tickets[r] = srv.submit(t)
+            ready.release()
+            if r % 2000 == 1999:
+                log(f"serve: {r + 1} of {count} submitted at {time.perf_counter() - t0:.2f} s")
+        submit_s = time.perf_counter() - t0
+        th.join()
         wall = time.perf_counter() - t0
         st = srv.stats()
     keys = int(sizes.sum())
-    ok = all(rc == 0 for rc in rcs) and all(torch.equal(t, ref) for t, ref in zip(reqs, refs))
-    return {"stream": "reduced: 120 requests, sizes log-uniform [1e3, 1e5], 70 % FP64, 2000/s, "
-                      "32 in flight, 1 GiB budget",
-            "requests": count, "keys": keys, "wall_s": wall, "keys_per_s": keys / wall,
+    return {"requests": count, "keys": keys, "wall_s": wall, "submit_s": submit_s, "keys_per_s": keys / wall,
             "keys_per_busy_s": keys / st["busy_s"] if st["busy_s"] > 0 else None,
             "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
-            "completed": st["completed"], "failed": st["failed"], "verified": bool(ok)}
+            "mean_latency_s": st["mean_latency_s"], "ticks": st["ticks"],
+            "completed": st["completed"], "failed": st["failed"],
+            "verified_sorted_and_permutation": not bad and all(c == 0 for c in codes),
+            "_kept": kept}
+
+
+def serve_leg(ksort, torch, count: int = 20_000, sat_count: int = 2_000, sample: int = 200) -> dict:
+    """The serving workload: a seeded Poisson stream of `count` requests,
+    sizes log-uniform in [1e3, 1e7] (seed 12), 70 % FP64 (seed 13),
+    arrivals from seed 11 at lambda = 0.7 x the plain path's keys/s on this
+    size mix / E[n], 256 in flight under a 64 GiB budget.  Each request's
+    keys are drawn on the device (a producer stream) at its arrival, while
+    the server runs.  Every result is checked sorted and a permutation of
+    its input (bit-pattern checksums); a seeded sample of `sample` requests
+    is checked against torch.sort, the oracle (with its first pivot) and
+    its result when sorted alone.  Then a saturation run: the first
+    `sat_count` requests, drawn beforehand, all submitted at t = 0."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    import synth
+    lo, hi, p64 = 1_000, 10_000_000, 0.7
+    sizes, is_f64, _ = synth.serve_requests(count, 12, 13, 11, lo, hi, p64, 1.0)
+    kinds = ["uniform_f64" if f else "uniform_f32" for f in is_f64]
+    e_n = (hi - lo) / (np.log(hi) - np.log(lo))  # mean of the log-uniform size
+    plain = _plain_rate(ksort, torch, sizes, kinds, 400)
+    lam = 0.7 * plain / e_n
+    _, _, arrivals = synth.serve_requests(count, 12, 13, 11, lo, hi, p64, lam)
+    rng = np.random.default_rng(14)
+    picks = sorted(int(x) for x in rng.choice(count, size=min(sample, count), replace=False))
+    log(f"serve: plain path {plain / 1e9:.2f} G keys/s on the size mix; lambda {lam:.0f} requests/s")
+    res = _run_stream(ksort, torch, sizes, kinds, arrivals, 64 << 30, 256, keep=set(picks))
+    kept = res.pop("_kept")
+    log(f"serve: stream done in {res['wall_s']:.2f} s; checking {len(picks)} sampled requests")
+    # the sample: torch.sort, the oracle with the first pivot, and alone
+    ok_sample = True
+    with ksort.Server(64 << 30, 256) as srv_alone:
+        alone_pivots = {}
+        for r in picks:
+            t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
+            ok_sample = ok_sample and torch.equal(kept[r], torch.sort(t)[0])
+            tk = srv_alone.submit(t)
+            ok_sample = ok_sample and srv_alone.wait(tk, 60.0) == 0
+            ok_sample = ok_sample and torch.equal(t, kept[r])
+            alone_pivots[r] = srv_alone.result(tk)["first_pivot"]
+            srv_alone.release(tk)
+
+    def oracle_check(r):
+        a = (synth.uniform_f64 if is_f64[r] else synth.uniform_f32)(synth.REQUEST_SEED_BASE + r, int(sizes[r]))
+        want, wp = oracle.sorted_copy(a)
+        got = kept[r].cpu().numpy()
+        return np.array_equal(got.view(np.uint8), want.view(np.uint8)) and wp == alone_pivots[r]
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)))) as ex:
+        ok_oracle = all(ex.map(oracle_check, picks))
+    del kept
+    torch.cuda.empty_cache()
+    # saturation: the first sat_count requests, all at t = 0
+    pre = []
+    for r in range(sat_count):
+        t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
+        pre.append((t, _bits_checksum(torch, t)))
+    torch.cuda.synchronize()
+    sat = _run_stream(ksort, torch, sizes[:sat_count], kinds[:sat_count], np.zeros(sat_count), 64 << 30, 256,
+                      pre_drawn=pre)
+    sat.pop("_kept")
+    del pre
+    torch.cuda.empty_cache()
+    res.update({"workload": "c4: Poisson stream, sizes log-uniform [1e3, 1e7] (seed 12), 70 % FP64 (seed 13), "
+                            "arrivals seed 11, keys of request r from seed 1,000,000 + r drawn on the device at "
+                            "arrival, 256 in flight, 64 GiB budget",
+                "lambda_per_s": lam, "plain_keys_per_s_on_mix": plain,
+                "plain_rate_sample": "first 400 requests of the mix, one plain call each",
+                "sample_checked": len(picks), "sample_equal_torch_sort_and_alone": bool(ok_sample),
+                "sample_equal_oracle_with_first_pivot": bool(ok_oracle),
+                "saturation": dict(sat, workload=f"first {sat_count} requests of the stream, drawn beforehand, "
+                                                  "all submitted at t = 0")})
+    res["verified"] = bool(res["verified_sorted_and_permutation"] and ok_sample and ok_oracle
+                           and sat["verified_sorted_and_permutation"])
+    return res
 
 
 TABLE1_N = [100_000, 500_000, 1_000_000, 2_500_000, 5_000_000, 6_000_000, 7_000_000, 7_100_000, 7_500_000,

@@ -30,6 +30,7 @@ struct Variant {
   int dtype;
   int block, items, cutoff;
   const void* stage;      // stage_kernel<T, BLOCK, ITEMS, CUT>
+  hipError_t (*launch)(const StageArgs& a, int grid, hipStream_t stream);  // enqueues it
   size_t key_bytes;
   int tile() const { return block * items; }
 };

@@ -50,6 +50,29 @@ constexpr int kWave = 64;
 // register instead of flat accesses with 64-bit per-lane addresses.
 #define KS_GLOBAL __attribute__((address_space(1)))
 
+// Compiler-level helpers written as inline assembly.  A build may define
+// them beforehand (the host test build of the kernels does).
+//   KS_OPAQUE(x)  : x passes through an empty asm in a vector register, so the
+//                   optimizer cannot recompute or hoist what it depends on
+//   KS_LDS_WAIT() : wait until this wave's LDS operations have completed
+//   KS_MEM_FENCE(): a compiler-only memory barrier
+//   KS_WAVE_STEP(): marks a point where the code relies on the lanes of a wave
+//                   executing in step (a lane reads what other lanes of its
+//                   wave wrote to LDS just before); no instruction on the
+//                   hardware, where a wave always executes in step
+#ifndef KS_OPAQUE
+#define KS_OPAQUE(x) asm volatile("" : "+v"(x))
+#endif
+#ifndef KS_LDS_WAIT
+#define KS_LDS_WAIT() asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory")
+#endif
+#ifndef KS_MEM_FENCE
+#define KS_MEM_FENCE() asm volatile("" ::: "memory")
+#endif
+#ifndef KS_WAVE_STEP
+#define KS_WAVE_STEP()
+#endif
+
 template <typename T>
 __device__ __forceinline__ T gld(const void* base, uint32_t byte_off) {
   return *(const KS_GLOBAL T*)((const KS_GLOBAL char*)base + byte_off);
@@ -556,7 +579,7 @@ __device__ int partition_one(const StageArgs& a, const TaskU& tk, PartSmem<T, BL
   // Opaque to the optimizer: keeps per-item offsets from being hoisted out of
   // the persistent loop, where they would hold dozens of registers for its
   // whole duration.
-  asm volatile("" : "+v"(tid));
+  KS_OPAQUE(tid);
   const int lane = tid & (kWave - 1), w = tid / kWave;
 
   const int32_t tidx = tk.t - tk.first_tile;
@@ -665,7 +688,8 @@ __device__ int partition_one(const StageArgs& a, const TaskU& tk, PartSmem<T, BL
   // since the counting loop (a compare costs less than the registers).
   T key2 = key;
   int tid2 = tid;
-  asm volatile("" : "+v"(key2), "+v"(tid2));
+  KS_OPAQUE(key2);
+  KS_OPAQUE(tid2);
   // this wave's offsets, one per lane as when they were counted
   const int woff = lane < ITEMS ? sm.off_lt[lane * NW + w] : lane < 2 * ITEMS ? sm.off_ge[(lane - ITEMS) * NW + w] : 0;
 #pragma unroll
@@ -755,7 +779,7 @@ template <typename T, typename In>
 __device__ void wave_rank_sort(const In* in, T* out, int L, int64_t* pivot_slot, int64_t pivot_bias) {
   const int lane = lane_id();
   T v = lane < L ? (T)in[lane] : T(0);
-  asm volatile("" : "+v"(v));
+  KS_OPAQUE(v);
   int rank = 0;
   int j = 0;
   if (__ballot(lane < L && v != v) == 0) {
@@ -840,7 +864,7 @@ __device__ void lds_rank_sort(const T* in, T* out, int L, int32_t* tie) {
   if (wave_sum(sum) != L * (L - 1) / 2) {
 #pragma unroll
     for (int k = 0; k < K; ++k) tie[lane + kWave * k] = 0;
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the counters are clear before any increment
+    KS_LDS_WAIT();  // the counters are clear before any increment
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (lane + kWave * k < L) rank[k] += atomicAdd(&tie[rank[k]], 1);
@@ -1038,7 +1062,7 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
           __builtin_amdgcn_s_sleep(1);
         }
         if (e == 0) break;  // everything is done
-        asm volatile("" ::: "memory");  // the side's keys are read only after its entry
+        KS_MEM_FENCE();  // the side's keys are read only after its entry
       }
       const int p = (e >> 1) & 1, s = (e >> 2) & 0xfff, L = (int)(e >> 14);
       int pushed = 0;
@@ -1055,6 +1079,7 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
         const T key = sm.buf[p][s];
         const int cl = wave_partition<T>(sm.buf[p], sm.buf[p ^ 1], s, L, key);
         const int cg = L - 1 - cl;
+        KS_WAVE_STEP();  // lane 0 and the next partitions read keys the other lanes just wrote
         if (lane == 0) gst<T>(dst, (uint32_t)((s + cl) * sizeof(T)), key);  // Step-4: the key is final
         // Steps 5-6 on the two sides (a side of one key is final)
         if (cl == 1 && lane == 0) gst<T>(dst, (uint32_t)(s * sizeof(T)), sm.buf[p ^ 1][s]);
@@ -1066,18 +1091,19 @@ __device__ void finish_segment(const StageArgs& a, const TaskU& tk, FinSmem<T, B
         const bool keep_lt = el != 0 && (eg == 0 || cl <= cg);
         keep = keep_lt ? el : eg;
         const uint32_t give = keep_lt ? eg : el;
-        if (give != 0 && lane == 0) {
+        if (give != 0) {
           // the side's keys (written by this wave) are in LDS before its entry
-          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-          const int qi = atomicAdd(&sm.q_tail, 1);
-          __hip_atomic_store(&sm.q[qi], give, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          KS_LDS_WAIT();
+          if (lane == 0) {
+            const int qi = atomicAdd(&sm.q_tail, 1);
+            __hip_atomic_store(&sm.q[qi], give, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
         }
       }
       // new entries are written before this update
-      if (lane == 0) {
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      KS_LDS_WAIT();
+      if (lane == 0)
         __hip_atomic_fetch_add(&sm.outstanding, pushed - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
       e = (uint32_t)uniform((int)keep);
     }
     __syncthreads();

@@ -57,6 +57,10 @@ static Variant make_variant(int dtype) {
   v.items = ITEMS;
   v.cutoff = CUT;
   v.stage = (const void*)&stage_kernel<T, BLOCK, ITEMS, CUT>;
+  v.launch = [](const StageArgs& a, int grid, hipStream_t stream) -> hipError_t {
+    hipLaunchKernelGGL((stage_kernel<T, BLOCK, ITEMS, CUT>), dim3(grid), dim3(BLOCK), 0, stream, a);
+    return hipGetLastError();
+  };
   v.key_bytes = sizeof(T);
   return v;
 }
@@ -469,8 +473,7 @@ int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid) 
   // unless the caller chose otherwise, one round of finish tasks on the grid
   // in a stage that also partitions
   if (args.fin_run <= 0) args.fin_run = KSORT_FIN_RUN(grid);
-  void* params[] = {&args};
-  KSORT_HIP(hipLaunchKernel(v.stage, dim3(grid), dim3(v.block), params, 0, ws.stream));
+  KSORT_HIP(v.launch(args, grid, ws.stream));
   return KSORT_OK;
 }
 

@@ -1,0 +1,63 @@
+"""The library on the host (no GPU): its own sources (host driver, server
+and kernels) compiled with g++ against tests/cpu_sim/hip/hip_runtime.h, a
+small HIP runtime that runs each workgroup's threads as fibers on a CPU
+thread and keeps guard pages around every device allocation.
+
+* plain sorts of arrays spanning many tiles against std::sort, with the
+  first pivot against its closed form;
+* the server with slot, scratch and buffer reuse over hundreds of requests
+  of mixed sizes and key types, 256 in flight;
+* the same with asynchronous in-order queues shared by several streams
+  (a producer and a checker stream beside the server's), with and without
+  kernels of those streams competing for the workgroup slots of the device.
+"""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1107_3622_amd", "csrc")
+SIM = os.path.join(ROOT, "tests", "cpu_sim")
+LIB_SOURCES = [os.path.join(CSRC, f) for f in ("ksort_lib.hip", "ksort_server.hip", "ksort_tune.hip")]
+
+
+@pytest.fixture(scope="module")
+def sim_build(tmp_path_factory):
+    out = tmp_path_factory.mktemp("ksim")
+    exes = {}
+    for drv in ("plain_sim", "server_sim", "serve_async_sim"):
+        exe = out / drv
+        subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-rdynamic", "-Wall",
+                        "-Wno-attributes", "-Wno-unknown-pragmas", "-Wno-unused-function",
+                        "-I", SIM, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                        "-x", "c++", *LIB_SOURCES, "-x", "none", os.path.join(SIM, "ksim.cpp"),
+                        os.path.join(SIM, drv + ".cpp"), "-o", str(exe), "-lpthread"], check=True)
+        exes[drv] = str(exe)
+    return exes
+
+
+def run(exe, args, env_extra, timeout=600):
+    env = dict(os.environ, KSIM_CUS="4", KSIM_OCC="2", **env_extra)
+    r = subprocess.run([exe, *map(str, args)], capture_output=True, text=True, env=env, timeout=timeout)
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    return r.stdout
+
+
+@pytest.mark.parametrize("n", [1000, 70_000, 300_000])
+def test_plain_sorts_on_the_host_build(sim_build, n):
+    assert "ok" in run(sim_build["plain_sim"], [n], {})
+
+
+def test_server_reuse_on_the_host_build(sim_build):
+    out = run(sim_build["server_sim"], [400, 1000, 20000, 256, 1024, 500], {})
+    assert "400 completed, 0 failed" in out and "0 wrong" in out
+
+
+@pytest.mark.parametrize("hwq,slots", [(4, None), (1, None), (4, 8)])
+def test_server_with_async_queues_on_the_host_build(sim_build, hwq, slots):
+    env = {"KSIM_HWQ": str(hwq)}
+    if slots:
+        env["KSIM_SLOTS"] = str(slots)
+    out = run(sim_build["serve_async_sim"], [120, 1000, 20000, 256, 1024, 2000], env)
+    assert "120 completed, 0 failed" in out and "0 wrong" in out
