@@ -270,6 +270,26 @@ KSORT_API size_t ksort_workspace_bytes(int dtype, int64_t n, int64_t nseg);
  * KSORT_EHIP. */
 KSORT_API int ksort_set_workspace(void *d_ws, size_t bytes, void *stream);
 
+/* ksort_sort_static: ksort_sort_ex (default variant) for callers that cannot
+ * allocate memory: code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Its scratch (descriptor lists, counters, flags,
+ * look-back words and the ping-pong keys) is a file-scope device array of
+ * KSORT_STATIC_SCRATCH_BYTES (64 MiB) that every GPU the library runs on
+ * holds until the process ends; the call makes no hipMalloc, hipHostMalloc,
+ * hipFree or other allocating call (the first call on a device looks up the
+ * array's device address and the device's properties once).
+ *   dtype, d_data, n, d_first_pivot, stream: as ksort_sort_ex.
+ * Limit: the sort's scratch must fit the array: at most 7,835,072 FP64 or
+ * 14,909,568 FP32 keys.  A larger n fails with KSORT_ETOOLARGE before any
+ * device work, and ksort_last_error() gives the exact maximum.
+ * Calls on one device share the array: the library serializes them (each
+ * returns after its work is complete), and a call leaves its contents
+ * behind; what must start at zero is cleared by each call.  Work of two
+ * processes, or a call recorded into a graph, would race on it: not
+ * supported.  Errors: as ksort_sort_ex, and KSORT_ETOOLARGE. */
+#define KSORT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+KSORT_API int ksort_sort_static(int dtype, void *d_data, int64_t n, int64_t *d_first_pivot, void *stream);
+
 /* Releases every cached workspace of the calling process (all devices).
  * Memory given with ksort_set_workspace is not freed (it is the caller's);
  * the streams go back to library-owned memory. */

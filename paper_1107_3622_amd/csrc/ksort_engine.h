@@ -83,7 +83,8 @@ struct Workspace {
   uint32_t epoch = 0;         // last epoch used
   int64_t epoch_span = (1 << 22) - 1;  // look-back tags of this run (see ksort_epoch.h)
   uint64_t generation = 0;    // bumped whenever the arena or the scratch is laid out anew
-  Flags* h_flags = nullptr;   // pinned readback
+  Flags* h_flags = nullptr;   // pinned readback (or memory the owner of the workspace provides)
+  bool own_h_flags = true;    // h_flags was allocated by reserve() and is freed with the workspace
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   std::vector<hipEvent_t> events; // pool for per-level timing (profiling mode)
   void* user = nullptr;        // caller's device memory (ksort_set_workspace), or null

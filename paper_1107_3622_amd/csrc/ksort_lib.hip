@@ -205,7 +205,7 @@ Workspace::~Workspace() {
     if (arena) (void)hipFree(arena);
     if (scratch) (void)hipFree(scratch);
   }
-  if (h_flags) (void)hipHostFree(h_flags);
+  if (h_flags && own_h_flags) (void)hipHostFree(h_flags);
 }
 
 // Lays out the descriptor lists, counters, flags and look-back words in
@@ -586,6 +586,10 @@ static int longest_array(const int64_t* d_offsets, int64_t nseg, int64_t n, hipS
   return KSORT_OK;
 }
 
+static int sort_in(Workspace& ws, const Variant& v, const DeviceInfo& di, int dtype, void* d_data, int64_t n,
+                   const int64_t* d_offsets, int64_t nseg, int64_t* d_pivots, hipStream_t stream, bool use_graph,
+                   bool allow_profiling);
+
 int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64_t nseg, int64_t* d_pivots,
              const ksort_tuning* tune, hipStream_t stream, bool use_graph) {
   if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
@@ -613,11 +617,22 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
 
   Workspace& ws = *workspace_for(dev, stream);
   std::lock_guard<std::mutex> lk(ws.mu);
+  return sort_in(ws, *v, *di, dtype, d_data, n, d_offsets, nseg, d_pivots, stream, use_graph, true);
+}
+
+// The level loop of one sort in workspace ws (whose lock the caller holds).
+static int sort_in(Workspace& ws, const Variant& vv, const DeviceInfo& dinfo, int dtype, void* d_data, int64_t n,
+                   const int64_t* d_offsets, int64_t nseg, int64_t* d_pivots, hipStream_t stream, bool use_graph,
+                   bool allow_profiling) {
+  const Variant* v = &vv;
+  const DeviceInfo* di = &dinfo;
+  const int dev = di->ordinal;
+  ws.stream = stream;
   const Caps caps = caps_for(*v, n, nseg, false);
-  rc = ws.reserve(caps, (size_t)std::max<int64_t>(n, 1) * v->key_bytes);
+  int rc = ws.reserve(caps, (size_t)std::max<int64_t>(n, 1) * v->key_bytes);
   if (rc) return rc;
   const int grid = stage_grid(*v, *di, ws.caps);
-  const bool prof = profiling_on();
+  const bool prof = allow_profiling && profiling_on();
   ws.stats = prof;
   ws.epoch_span = epoch_span_setting();
   const int64_t call = next_call_id();
@@ -767,6 +782,99 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
   return KSORT_OK;
 }
 
+// ---------------------------------------------------------------- static scratch
+//
+// Scratch for callers that cannot allocate: one file-scope device array per
+// GPU, holding the descriptor lists, counters, flags, look-back words and
+// the ping-pong keys of one sort.  Host code never uses the array's name as
+// an address: the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+
+constexpr size_t kStaticScratchBytes = KSORT_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char g_static_scratch[kStaticScratchBytes];
+
+struct StaticSlot {
+  std::mutex mu;
+  bool ready = false;
+  void* ptr = nullptr;  // this device's copy of g_static_scratch
+  Workspace ws;
+  Flags h_flags;        // flags are read back into this (pageable) word
+};
+constexpr int kMaxStaticDevices = 64;
+static StaticSlot g_static[kMaxStaticDevices];
+
+// Bytes of static scratch a sort of n keys with variant v takes.
+static size_t static_bytes_for(const Variant& v, const Caps& c, int64_t n) {
+  return align256(arena_bytes_for(c, (int)c.stats)) + align256((size_t)std::max<int64_t>(n, 1) * v.key_bytes);
+}
+
+// The largest n whose sort fits the static scratch (the variant chosen for
+// each n as a plain sort would choose it).
+static int64_t static_max_keys(int dtype) {
+  int64_t lo = 1, hi = (int64_t)(kStaticScratchBytes / (dtype == KSORT_F64 ? 8 : 4)) + 1;
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    const Variant* v = find_variant(dtype, nullptr, mid);
+    if (static_bytes_for(*v, caps_for(*v, mid, 1, false), mid) <= kStaticScratchBytes)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+static int sort_static(int dtype, void* d_data, int64_t n, int64_t* d_pivot, hipStream_t stream) {
+  if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
+  if (n < 0) return fail(KSORT_EINVAL, "negative size");
+  if (n > 0 && !d_data) return fail(KSORT_EINVAL, "null data pointer");
+  if (n <= 1) {
+    if (d_pivot) {
+      const int64_t fp = n == 0 ? -1 : 0;
+      KSORT_HIP(hipMemcpyAsync(d_pivot, &fp, sizeof fp, hipMemcpyHostToDevice, stream));
+      KSORT_HIP(hipStreamSynchronize(stream));
+    }
+    return KSORT_OK;
+  }
+  const Variant* v = find_variant(dtype, nullptr, n);
+  const Caps c = caps_for(*v, n, 1, false);
+  if (static_bytes_for(*v, c, n) > kStaticScratchBytes)
+    return fail(KSORT_ETOOLARGE, "a sort of " + std::to_string(n) + " keys needs " +
+                                     std::to_string(static_bytes_for(*v, c, n)) + " bytes of scratch; the static " +
+                                     "scratch holds " + std::to_string(kStaticScratchBytes) + " (at most " +
+                                     std::to_string(static_max_keys(dtype)) + " keys of this type)");
+  int dev = 0;
+  KSORT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxStaticDevices) return fail(KSORT_EUNSUPPORTED, "device ordinal beyond the static slots");
+  const DeviceInfo* di = nullptr;
+  int rc = device_info(dev, &di);
+  if (rc) return rc;
+  if (!di->gfx950) return fail(KSORT_EUNSUPPORTED, "device " + std::to_string(dev) + " is " + di->arch + ", not gfx950");
+  StaticSlot& sl = g_static[dev];
+  std::lock_guard<std::mutex> lk(sl.mu);
+  if (!sl.ready) {
+    // set-up, once per device with that device current
+    void* p = nullptr;
+    KSORT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(g_static_scratch)));
+    sl.ptr = p;
+    sl.ws.device = dev;
+    sl.ws.user = sl.ptr;
+    sl.ws.user_bytes = kStaticScratchBytes;
+    sl.ws.h_flags = &sl.h_flags;
+    sl.ws.own_h_flags = false;
+    sl.ready = true;
+  }
+  // The lists keep the largest capacities of earlier calls; when those and
+  // this call's keys do not fit together, lay the lists out for this call.
+  Caps grown = sl.ws.caps;
+  grown.live = std::max(grown.live, c.live);
+  grown.tiles = std::max(grown.tiles, c.tiles);
+  grown.fin = std::max(grown.fin, c.fin);
+  grown.bufs = std::max(grown.bufs, c.bufs);
+  grown.stats = std::max(grown.stats, c.stats);
+  if (static_bytes_for(*v, grown, n) > kStaticScratchBytes) sl.ws.caps = Caps{};
+  return sort_in(sl.ws, *v, *di, dtype, d_data, n, nullptr, 1, d_pivot, stream, false, false);
+}
+
 static int run_level(int dtype, const void* d_in, void* d_out, int64_t n, const int64_t* d_left,
                      const int64_t* d_len, int64_t nseg, int64_t* d_pivot, hipStream_t stream) {
   if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
@@ -831,6 +939,10 @@ extern "C" {
 int ksort_sort_ex(int dtype, void* d_data, int64_t n, int64_t* d_first_pivot, const ksort_tuning* tune,
                   void* stream) {
   return run_sort(dtype, d_data, n, nullptr, 1, d_first_pivot, tune, (hipStream_t)stream, false);
+}
+
+int ksort_sort_static(int dtype, void* d_data, int64_t n, int64_t* d_first_pivot, void* stream) {
+  return sort_static(dtype, d_data, n, d_first_pivot, (hipStream_t)stream);
 }
 
 int ksort_f64(double* d_data, int64_t n, void* stream) {

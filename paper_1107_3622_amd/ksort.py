@@ -72,6 +72,7 @@ SIGNATURES = {
     "ksort_f64": (_int, [_p, _i64, _p]),
     "ksort_f32": (_int, [_p, _i64, _p]),
     "ksort_sort_ex": (_int, [_int, _p, _i64, _p, _p, _p]),
+    "ksort_sort_static": (_int, [_int, _p, _i64, _p, _p]),
     "ksort_partition_level": (_int, [_int, _p, _p, _i64, _p, _p, _i64, _p, _p]),
     "ksort_segmented": (_int, [_int, _p, _i64, _p, _i64, _p, _p, _p]),
     "ksort_partition_level_exact": (_int, [_int, _p, _p, _i64, _p, _p, _i64, _p, _p]),
@@ -200,6 +201,16 @@ def ksort_sort_ex(t, first_pivot=None, tune=None, stream=None) -> None:
     tn = _tuning(tune)
     _check(load().ksort_sort_ex(_dtype_code(t), t.data_ptr(), t.numel(), fp, _ref(tn), _stream(stream)),
            "ksort_sort_ex")
+
+
+def ksort_sort_static(t, first_pivot=None, stream=None) -> None:
+    """Sort in place with the library's static scratch (no allocation)."""
+    _check_keys(t)
+    if first_pivot is not None:
+        _check_index_out(first_pivot, 1, "first_pivot")
+    fp = first_pivot.data_ptr() if first_pivot is not None else None
+    _check(load().ksort_sort_static(_dtype_code(t), t.data_ptr(), t.numel(), fp, _stream(stream)),
+           "ksort_sort_static")
 
 
 def sort_(t, tune=None, stream=None) -> int:

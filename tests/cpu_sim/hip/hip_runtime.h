@@ -100,6 +100,9 @@ void ksim_launch_args(hipStream_t s, dim3 grid, dim3 block, F f, A... a) {
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static thread_local  // one CPU thread runs one workgroup at a time
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(x) (&(x))
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);
 
 struct ksim_dims {
   dim3 tid, bid, bdim, gdim;
