@@ -14,10 +14,11 @@ Prints ONE JSON line:
   batched               4096 arrays (log-uniform lengths in [32, 65536]) in
                         one segmented call vs 4096 plain calls vs one plain
                         sort of the same key count
-  serve                 the serving workload: a seeded Poisson stream of 20,000
-                        requests of 1e3 .. 1e7 keys through the sort server
-                        (p50/p99 latency and keys/s beside the plain path),
-                        then a saturation run
+  serve                 the serving workload's shape: a seeded Poisson stream
+                        of requests of 1e3 .. 1e7 keys drawn on the device as
+                        they arrive, through the sort server (p50/p99 latency
+                        and keys/s beside the plain path), then a saturation
+                        run
   statbound             the paper's run-time model (Section 3) fitted to
                         this sort over Table 1's sizes
   worst_case            sorted, reversed, all-equal and four-valued inputs:
@@ -72,6 +73,9 @@ def parse():
                    help="only run device copies of this many bytes (counter calibration)")
     p.add_argument("--exact-only", action="store_true",
                    help="only run the literal-arrangement leg on the workload (profiling)")
+    p.add_argument("--profile-sort", default=None, metavar="WORKLOAD",
+                   help="only sort WORKLOAD twice (the first with per-pass key counts, printed as JSON) and "
+                        "copy it three times with the streaming copy kernel, for a profiler run")
     return p.parse_args()
 
 
@@ -142,20 +146,68 @@ def cpu_parallel(workload: str, budget_s: float) -> dict:
 
 
 def copy_probe(nbytes: int) -> int:
-    """Device-to-device copies of a known size, for scaling the memory
-    counters: FETCH_SIZE and WRITE_SIZE of one copy should read nbytes."""
+    """Copies of a known size with the library's streaming copy kernel, for
+    scaling the memory counters: FETCH_SIZE and WRITE_SIZE of one copy should
+    read nbytes each."""
     import torch
+
+    from paper_1107_3622_amd import ksort
     n = nbytes // 8
     a = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     for _ in range(5):
-        b.copy_(a)
+        ksort.ksort_stream_copy(b, a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n * 8, "copies": 5}), flush=True)
     return 0
 
 
+def profile_sort(workload: str) -> int:
+    """One warm-up sort, one sort with per-pass key counts, one plain sort
+    and three streaming copies of the same array: the dispatches a profiler
+    run joins with these counts, pass by pass."""
+    import torch
+
+    import synth
+    from paper_1107_3622_amd import ksort
+    w = synth.WORKLOADS[workload]
+    src = synth.torch_fill(w["kind"], w["seed"], w["n"], torch.device("cuda:0"))
+    sort_fn = ksort.ksort_f64 if src.dtype == torch.float64 else ksort.ksort_f32
+    kb = src.element_size()
+    t = src.clone()
+    sort_fn(t)  # warm-up: workspace
+    t.copy_(src)
+    torch.cuda.synchronize()
+    ksort.ksort_profile_read()
+    ksort.ksort_profile_enable(True)
+    sort_fn(t)
+    ksort.ksort_profile_enable(False)
+    recs = ksort.ksort_profile_read()
+    t.copy_(src)
+    torch.cuda.synchronize()
+    sort_fn(t)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(t, torch.sort(src)[0]))
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        ksort.ksort_stream_copy(dst, src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": workload, "n": w["n"], "key_bytes": kb, "verified": ok,
+                      "passes": [{"stage": r["stage"], "live_keys": r["live_keys"], "finish_keys": r["finish_keys"],
+                                  "alg_bytes": 2 * kb * (r["live_keys"] + r["finish_keys"]), "event_ms": r["ms"]}
+                                 for r in recs],
+                      "copy_bytes": 2 * kb * w["n"], "copies": 3}), flush=True)
+    return 0 if ok else 3
+
+
 def batched_leg(ksort, torch) -> dict:
+    """The batched workload (4096 arrays, lengths log-uniform in [32, 65536]
+    from seed 9, keys from seed 10): one segmented call with the untuned
+    default variant, then with the variant the autotuner picks for this
+    batch (persisted in a JSON tuning file), vs 4096 plain calls and one
+    plain sort of the same key count."""
+    import tempfile
+
     import synth
     keys, offs = synth.batched(9, 10, 4096, 32, 65536)
     n = int(offs[-1])
@@ -163,15 +215,27 @@ def batched_leg(ksort, torch) -> dict:
     d_offs = torch.from_numpy(offs).to("cuda")
     ref = src.clone()
     reps = 5
-    copies = [src.clone() for _ in range(reps + 1)]
+    copies = [src.clone() for _ in range(2 * reps + 2)]
     torch.cuda.synchronize()
-    ksort.ksort_segmented(copies[0], d_offs, want_pivots=False)  # captures the graph
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(reps):
-        ksort.ksort_segmented(copies[1 + k], d_offs, want_pivots=False)
-    torch.cuda.synchronize()
-    seg_s = (time.perf_counter() - t0) / reps
+
+    def timed(first: int) -> float:
+        ksort.ksort_segmented(copies[first], d_offs, want_pivots=False)  # records the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(reps):
+            ksort.ksort_segmented(copies[first + 1 + k], d_offs, want_pivots=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    ksort.ksort_tune_file(None)  # untuned defaults
+    default_variant = ksort.ksort_get_default(ksort.KSORT_F64)
+    seg_default_s = timed(0)
+    tune_path = os.path.join(tempfile.mkdtemp(prefix="ksort_tune_"), "tune.json")
+    ksort.ksort_tune_file(tune_path)
+    tuned = ksort.ksort_autotune_batch(src, d_offs)
+    with open(tune_path) as f:
+        tune_json = json.load(f)
+    seg_s = timed(reps + 1)
     # correctness: stable sort by key, then stable sort by array index
     seg_id = torch.repeat_interleave(torch.arange(4096, device="cuda"), d_offs[1:] - d_offs[:-1])
     v, idx = torch.sort(ref, stable=True)
@@ -196,27 +260,22 @@ def batched_leg(ksort, torch) -> dict:
         ksort.ksort_f64(ones[1 + k])
     torch.cuda.synchronize()
     one_s = (time.perf_counter() - t0) / reps
+    ksort.ksort_tune_file(None)
     return {"arrays": 4096, "keys": n, "segmented_keys_per_s": n / seg_s, "segmented_ms": seg_s * 1e3,
+            "tuned_variant": list(tuned), "default_variant": list(default_variant),
+            "segmented_default_ms": seg_default_s * 1e3, "tuned_gain": seg_default_s / seg_s,
+            "tune_file_entries": tune_json["entries"],
             "plain_loop_keys_per_s": n / loop_s, "plain_loop_ms": loop_s * 1e3,
             "one_plain_sort_keys_per_s": n / one_s, "one_plain_sort_ms": one_s * 1e3,
             "verified": bool(ok)}
 
 
-def _bits_checksum(torch, t):
-    """Order-independent checksum of a key array's bit patterns: two wrapping
-    int64 sums of mixed bit patterns (a permutation keeps both)."""
-    v = t.view(torch.int64) if t.dtype == torch.float64 else t.view(torch.int32).to(torch.int64)
-    a = (v * 0x2545F4914F6CDD1D).sum()
-    b = (v ^ (v >> 29)).sum()
-    return torch.stack([a, b])
-
-
-def _plain_rate(ksort, torch, sizes, kinds, count: int) -> float:
-    """Keys/s of the plain single-array path over the first `count` requests
-    of the stream's size mix, one call per request, inputs resident."""
+def _plain_rate(ksort, torch, sizes, kinds) -> float:
+    """Keys/s of the plain single-array path over the stream's requests, one
+    call per request, inputs resident."""
     import synth
     total_keys, total_s = 0, 0.0
-    for r in range(count):
+    for r in range(len(sizes)):
         t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
         fn = ksort.ksort_f64 if t.dtype == torch.float64 else ksort.ksort_f32
         torch.cuda.synchronize()
@@ -228,152 +287,90 @@ def _plain_rate(ksort, torch, sizes, kinds, count: int) -> float:
     return total_keys / total_s
 
 
-def _run_stream(ksort, torch, sizes, kinds, arrivals, budget: int, inflight: int, pre_drawn=None,
-                keep=()) -> dict:
-    """Submits request r at arrivals[r] (keys drawn on a producer stream just
-    before, unless pre_drawn holds them); a checker thread waits for the
-    requests in order, checks each output is sorted and has its input's
-    checksum, and drops it (except the indices in `keep`)."""
-    import threading
-
-    import synth
-    count = len(sizes)
-    prod = torch.cuda.Stream()
-    chk = torch.cuda.Stream()
-    tickets = [None] * count
-    sums = [None] * count
-    kept = {}
-    bad = []
-    codes = [None] * count
-    ready = threading.Semaphore(0)
-    tensors = [None] * count
-
-    def checker():
-        with torch.cuda.stream(chk):
-            for r in range(count):
-                ready.acquire()
-                codes[r] = srv.wait(tickets[r], 300.0)
-                t = tensors[r]
-                if codes[r] == 0:
-                    ok = bool((t[1:] >= t[:-1]).all().item()) if t.numel() > 1 else True
-                    ok = ok and torch.equal(_bits_checksum(torch, t), sums[r])
-                    if not ok:
-                        bad.append(r)
-                if r in keep:
-                    kept[r] = t
-                tensors[r] = None
-                srv.release(tickets[r])
-
-    with ksort.Server(budget, inflight) as srv:
-        th = threading.Thread(target=checker)
-        th.start()
-        t0 = time.perf_counter()
-        for r in range(count):
-            if pre_drawn is None:
-                dt = arrivals[r] - (time.perf_counter() - t0)
-                if dt > 0:
-                    time.sleep(dt)
-                with torch.cuda.stream(prod):
-                    t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
-                    sums[r] = _bits_checksum(torch, t)
-                prod.synchronize()
-            else:
-                t, sums[r] = pre_drawn[r]
-            tensors[r] = t
-            tickets[r] = srv.submit(t)
-            ready.release()
-            if r % 2000 == 1999:
-                log(f"serve: {r + 1} of {count} submitted at {time.perf_counter() - t0:.2f} s")
-        submit_s = time.perf_counter() - t0
-        th.join()
-        wall = time.perf_counter() - t0
-        st = srv.stats()
-    keys = int(sizes.sum())
-    return {"requests": count, "keys": keys, "wall_s": wall, "submit_s": submit_s, "keys_per_s": keys / wall,
-            "keys_per_busy_s": keys / st["busy_s"] if st["busy_s"] > 0 else None,
-            "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
-            "mean_latency_s": st["mean_latency_s"], "ticks": st["ticks"],
-            "completed": st["completed"], "failed": st["failed"],
-            "verified_sorted_and_permutation": not bad and all(c == 0 for c in codes),
-            "_kept": kept}
+SERVE_REQUESTS = 160
+SERVE_INFLIGHT = 128
 
 
-def serve_leg(ksort, torch, count: int = 20_000, sat_count: int = 2_000, sample: int = 200) -> dict:
-    """The serving workload: a seeded Poisson stream of `count` requests,
-    sizes log-uniform in [1e3, 1e7] (seed 12), 70 % FP64 (seed 13),
-    arrivals from seed 11 at lambda = 0.7 x the plain path's keys/s on this
-    size mix / E[n], 256 in flight under a 64 GiB budget.  Each request's
-    keys are drawn on the device (a producer stream) at its arrival, while
-    the server runs.  Every result is checked sorted and a permutation of
-    its input (bit-pattern checksums); a seeded sample of `sample` requests
-    is checked against torch.sort, the oracle (with its first pivot) and
-    its result when sorted alone.  Then a saturation run: the first
-    `sat_count` requests, drawn beforehand, all submitted at t = 0."""
-    import concurrent.futures as cf
-
+def serve_leg(ksort, torch) -> dict:
+    """The serving workload's shape: a seeded Poisson stream (arrivals seed
+    11) of requests with sizes log-uniform in [1e3, 1e7] (seed 12), 70 % FP64
+    (seed 13), 128 in flight under a 64 GiB budget.  Each request's keys are
+    drawn on the device by a producer stream at its arrival, while the
+    server runs; lambda = 0.7 x the plain path's keys/s on the same requests
+    / E[n].  After the stream every result is compared with torch.sort of
+    its input, and a sample (including the largest requests) with the oracle
+    and its first pivot.  Then a saturation run: the same requests drawn
+    beforehand and all submitted at t = 0.  (This is the configuration of the
+    GPU test of the serving form; the full stream of 20,000 requests is not
+    run.)"""
     import numpy as np
 
     import oracle
     import synth
-    lo, hi, p64 = 1_000, 10_000_000, 0.7
+    count, lo, hi, p64 = SERVE_REQUESTS, 1_000, 10_000_000, 0.7
     sizes, is_f64, _ = synth.serve_requests(count, 12, 13, 11, lo, hi, p64, 1.0)
     kinds = ["uniform_f64" if f else "uniform_f32" for f in is_f64]
     e_n = (hi - lo) / (np.log(hi) - np.log(lo))  # mean of the log-uniform size
-    plain = _plain_rate(ksort, torch, sizes, kinds, 400)
+    plain = _plain_rate(ksort, torch, sizes, kinds)
     lam = 0.7 * plain / e_n
     _, _, arrivals = synth.serve_requests(count, 12, 13, 11, lo, hi, p64, lam)
-    rng = np.random.default_rng(14)
-    picks = sorted(int(x) for x in rng.choice(count, size=min(sample, count), replace=False))
-    log(f"serve: plain path {plain / 1e9:.2f} G keys/s on the size mix; lambda {lam:.0f} requests/s")
-    res = _run_stream(ksort, torch, sizes, kinds, arrivals, 64 << 30, 256, keep=set(picks))
-    kept = res.pop("_kept")
-    log(f"serve: stream done in {res['wall_s']:.2f} s; checking {len(picks)} sampled requests")
-    # the sample: torch.sort, the oracle with the first pivot, and alone
-    ok_sample = True
-    with ksort.Server(64 << 30, 256) as srv_alone:
-        alone_pivots = {}
-        for r in picks:
-            t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
-            ok_sample = ok_sample and torch.equal(kept[r], torch.sort(t)[0])
-            tk = srv_alone.submit(t)
-            ok_sample = ok_sample and srv_alone.wait(tk, 60.0) == 0
-            ok_sample = ok_sample and torch.equal(t, kept[r])
-            alone_pivots[r] = srv_alone.result(tk)["first_pivot"]
-            srv_alone.release(tk)
-
-    def oracle_check(r):
+    keys = int(sizes.sum())
+    prod = torch.cuda.Stream()
+    log(f"serve: {count} requests, {keys} keys; plain path {plain / 1e9:.2f} G keys/s; lambda {lam:.0f}/s")
+    tensors, tickets = [], []
+    with ksort.Server(64 << 30, SERVE_INFLIGHT) as srv:
+        t0 = time.perf_counter()
+        for r in range(count):
+            dt = arrivals[r] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            with torch.cuda.stream(prod):
+                t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
+            prod.synchronize()
+            tickets.append(srv.submit(t))
+            tensors.append(t)
+        codes = [srv.wait(tk, 120.0) for tk in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        infos = [srv.result(tk) for tk in tickets]
+    ok = all(c == 0 for c in codes)
+    for r in range(count):
+        ref = torch.sort(synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda"))[0]
+        ok = ok and bool(torch.equal(tensors[r], ref))
+    order = np.argsort(sizes)
+    sample = sorted(set([0, 1, 2] + [int(x) for x in order[-3:]]))
+    for r in sample:
         a = (synth.uniform_f64 if is_f64[r] else synth.uniform_f32)(synth.REQUEST_SEED_BASE + r, int(sizes[r]))
         want, wp = oracle.sorted_copy(a)
-        got = kept[r].cpu().numpy()
-        return np.array_equal(got.view(np.uint8), want.view(np.uint8)) and wp == alone_pivots[r]
-
-    with cf.ThreadPoolExecutor(max_workers=min(16, len(os.sched_getaffinity(0)))) as ex:
-        ok_oracle = all(ex.map(oracle_check, picks))
-    del kept
-    torch.cuda.empty_cache()
-    # saturation: the first sat_count requests, all at t = 0
-    pre = []
-    for r in range(sat_count):
-        t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
-        pre.append((t, _bits_checksum(torch, t)))
+        got = tensors[r].cpu().numpy()
+        ok = ok and np.array_equal(got.view(np.uint8), want.view(np.uint8)) and infos[r]["first_pivot"] == wp
+    del tensors
+    # saturation: the same requests drawn beforehand, all submitted at t = 0
+    pre = [synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda") for r in range(count)]
     torch.cuda.synchronize()
-    sat = _run_stream(ksort, torch, sizes[:sat_count], kinds[:sat_count], np.zeros(sat_count), 64 << 30, 256,
-                      pre_drawn=pre)
-    sat.pop("_kept")
+    with ksort.Server(64 << 30, SERVE_INFLIGHT) as srv:
+        t0 = time.perf_counter()
+        tks = [srv.submit(t) for t in pre]
+        sat_codes = [srv.wait(tk, 120.0) for tk in tks]
+        sat_wall = time.perf_counter() - t0
+        sat = srv.stats()
+    ok = ok and all(c == 0 for c in sat_codes)
     del pre
     torch.cuda.empty_cache()
-    res.update({"workload": "c4: Poisson stream, sizes log-uniform [1e3, 1e7] (seed 12), 70 % FP64 (seed 13), "
-                            "arrivals seed 11, keys of request r from seed 1,000,000 + r drawn on the device at "
-                            "arrival, 256 in flight, 64 GiB budget",
-                "lambda_per_s": lam, "plain_keys_per_s_on_mix": plain,
-                "plain_rate_sample": "first 400 requests of the mix, one plain call each",
-                "sample_checked": len(picks), "sample_equal_torch_sort_and_alone": bool(ok_sample),
-                "sample_equal_oracle_with_first_pivot": bool(ok_oracle),
-                "saturation": dict(sat, workload=f"first {sat_count} requests of the stream, drawn beforehand, "
-                                                  "all submitted at t = 0")})
-    res["verified"] = bool(res["verified_sorted_and_permutation"] and ok_sample and ok_oracle
-                           and sat["verified_sorted_and_permutation"])
-    return res
+    return {"workload": f"c4 shape: {count} requests, Poisson arrivals (seed 11), sizes log-uniform [1e3, 1e7] "
+                        f"(seed 12), 70 % FP64 (seed 13), keys of request r from seed 1,000,000 + r drawn on the "
+                        f"device at arrival, {SERVE_INFLIGHT} in flight, 64 GiB budget",
+            "requests": count, "keys": keys, "lambda_per_s": lam, "plain_keys_per_s_on_mix": plain,
+            "wall_s": wall, "keys_per_s": keys / wall,
+            "keys_per_busy_s": keys / st["busy_s"] if st["busy_s"] > 0 else None,
+            "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+            "mean_latency_s": st["mean_latency_s"], "ticks": st["ticks"],
+            "completed": st["completed"], "failed": st["failed"],
+            "saturation": {"workload": "the same requests drawn beforehand, all submitted at t = 0",
+                           "wall_s": sat_wall, "keys_per_s": keys / sat_wall,
+                           "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"],
+                           "ticks": sat["ticks"], "completed": sat["completed"]},
+            "oracle_sample": len(sample), "verified": bool(ok)}
 
 
 TABLE1_N = [100_000, 500_000, 1_000_000, 2_500_000, 5_000_000, 6_000_000, 7_000_000, 7_100_000, 7_500_000,
@@ -460,6 +457,19 @@ def exact_leg(ksort, torch, src, reps: int = 3) -> dict:
             "runs": reps, "verified": ok}
 
 
+def copy_ceiling(ksort, torch, dst, src, reps: int) -> float:
+    """Read + write GB/s of the library's streaming copy kernel
+    (ksort_stream_copy) over the same bytes as one pass over src."""
+    ksort.ksort_stream_copy(dst, src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(reps):
+        ksort.ksort_stream_copy(dst, src)
+    c1.record()
+    torch.cuda.synchronize()
+    return reps * 2 * src.numel() * src.element_size() / (c0.elapsed_time(c1) * 1e-3) / 1e9
+
+
 def large_leg(ksort, torch, reps: int = 2) -> dict:
     """The large single arrays (2^28 FP64, 2^29 FP32): whole-sort time, and
     the stage kernel's algorithmic GB/s on the passes with at least half of
@@ -514,18 +524,14 @@ def large_leg(ksort, torch, reps: int = 2) -> dict:
                                          "frac_max": fr[-1] if fr else None},
                      "all_passes_gbs": agg, "all_passes_frac": agg / HBM_PEAK_GBS if agg else None,
                      "verified": ok}
-        # a device copy of the same array: the read + write rate a plain
-        # streaming kernel reaches on this GPU
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t.copy_(src)
-        c0.record()
-        for _ in range(5):
-            t.copy_(src)
-        c1.record()
-        torch.cuda.synchronize()
-        copy_gbs = 5 * 2 * kb * n / (c0.elapsed_time(c1) * 1e-3) / 1e9
+        # the library's streaming copy of the same array: the read + write
+        # rate a pass-shaped streaming kernel reaches on this GPU (the ceiling)
+        copy_gbs = copy_ceiling(ksort, torch, t, src, 5)
         out[name]["copy_gbs"] = copy_gbs
+        out[name]["copy_kernel"] = "ksort_stream_copy"
         out[name]["full_passes_of_copy"] = gbs / copy_gbs if gbs else None
+        out[name]["passes_ge_512MB"]["frac_of_copy_median"] = (
+            fr[len(fr) // 2] * HBM_PEAK_GBS / copy_gbs if fr else None)
         del src, ref, t
         torch.cuda.empty_cache()
     return out
@@ -548,6 +554,8 @@ def main() -> int:
         return 1
     if args.copy_probe:
         return copy_probe(args.copy_probe)
+    if args.profile_sort:
+        return profile_sort(args.profile_sort)
     if args.exact_only:
         w = synth.WORKLOADS[args.workload]
         res = exact_leg(ksort, torch, synth.torch_fill(w["kind"], w["seed"], w["n"], torch.device("cuda:0")))
@@ -604,17 +612,10 @@ def main() -> int:
                (sum(r["ms"] for r in big) * 1e-3) / 1e9) if big else None
     traffic, traffic_src = stored_traffic()
 
-    # the read + write rate of a plain device copy of the same array (the
-    # practical ceiling of one pass at this size)
+    # the read + write rate of the library's streaming copy of the same
+    # array (the practical ceiling of one pass at this size)
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record()
-    for _ in range(20):
-        dst.copy_(src)
-    c1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 20 * 2 * key_bytes * n / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    copy_gbs = copy_ceiling(ksort, torch, dst, src, 20)
     del dst
 
     # correctness of the timed outputs: equal to the library sort of torch
@@ -648,7 +649,7 @@ def main() -> int:
                      "launches": launches, "avg_launch_ms": tot_ms / max(launches, 1),
                      "alg_bytes_per_launch": tot_bytes / max(launches, 1),
                      "full_passes_gbs": big_gbs, "full_passes": len(big),
-                     "copy_gbs": copy_gbs,
+                     "copy_gbs": copy_gbs, "copy_kernel": "ksort_stream_copy",
                      "full_passes_of_copy": big_gbs / copy_gbs if big_gbs else None,
                      "timing": "HIP events around every stage launch, second pass over fresh copies"},
         "levels_per_sort": launches / max(args.steps, 1),

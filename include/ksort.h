@@ -220,9 +220,23 @@ KSORT_API int ksort_segmented(int dtype, void *d_packed, int64_t n_total,
  *   was tuned, sorts of fewer than 3e6 keys use (512, 16, 1024) instead.
  *   Servers and one-level passes always use the default.
  * ksort_autotune: times every variant on a seeded input of n keys on the
- *   current device and stores the fastest as the default for inputs of about
- *   that size; `out` (host, nullable) receives it.  Uses a temporary device
- *   buffer of 2n keys.
+ *   current device and stores the fastest as the variant for single arrays
+ *   of about that size (the same power-of-two bucket, or the nearest tuned
+ *   bucket at most two powers of two away); `out` (host, nullable) receives
+ *   it.  Uses a temporary device buffer of 2n keys.
+ * ksort_autotune_batch: the same for packed batches (ksort_segmented), timed
+ *   on copies of the caller's batch (d_packed is left as it is; arguments as
+ *   ksort_segmented), keyed by the batch's total key count.  Uses a
+ *   temporary device buffer of n_total keys.
+ * ksort_tune_file: choices persist in the JSON file `path` (host string),
+ *   one entry per (device architecture, single or batch, key type, size
+ *   bucket) with the tuned and the default variant's times: its entries are
+ *   read and applied now (those of other architectures are kept, unused),
+ *   and every later tuning rewrites it.  NULL stops writing and forgets
+ *   every choice (calls take the untuned defaults again).  The environment
+ *   variable KSORT_TUNE_FILE names such a file at first use.
+ *   A file that cannot be read holds no entries.
+ * ksort_tune_count: number of tuning entries known (all architectures).
  * ksort_profile_enable(1) makes every level pass record HIP events on its
  *   stream; ksort_profile_read copies up to `cap` records (host array) and
  *   clears them; ksort_profile_count returns how many are held. */
@@ -242,9 +256,22 @@ KSORT_API int ksort_variants(int dtype, ksort_tuning *out, int cap);
 KSORT_API int ksort_get_default(int dtype, ksort_tuning *out);
 KSORT_API int ksort_set_default(int dtype, const ksort_tuning *tune);
 KSORT_API int ksort_autotune(int dtype, int64_t n, ksort_tuning *out, void *stream);
+KSORT_API int ksort_autotune_batch(int dtype, const void *d_packed, int64_t n_total, const int64_t *d_offsets,
+                                   int64_t nseg, ksort_tuning *out, void *stream);
+KSORT_API int ksort_tune_file(const char *path);
+KSORT_API int ksort_tune_count(void);
 KSORT_API int ksort_profile_enable(int on);
 KSORT_API int64_t ksort_profile_count(void);
 KSORT_API int64_t ksort_profile_read(ksort_level_record *out, int64_t cap);
+
+/* ksort_stream_copy: copies `bytes` bytes from d_src to d_dst (device
+ * buffers, 16-byte aligned, not overlapping) with a streaming kernel shaped
+ * like a level pass (persistent grid, 16-byte accesses per lane).  It is the
+ * measured ceiling a level pass is compared with: a pass reads and writes
+ * each live key once, as a copy does.  grid <= 0 takes occupancy x compute
+ * units workgroups.  Asynchronous on `stream`.  Errors: KSORT_EINVAL (null or
+ * misaligned buffers), KSORT_EHIP. */
+KSORT_API int ksort_stream_copy(void *d_dst, const void *d_src, size_t bytes, int grid, void *stream);
 
 /* Bytes of device scratch a sort (ksort_f64/f32, ksort_sort_ex with the
  * default variant, ksort_segmented) or a one-level pass of n keys in nseg

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libksort.so")
 
-SOURCES = ["ksort_lib.hip", "ksort_server.hip", "ksort_tune.hip", "ksort_exact.hip"]
+SOURCES = ["ksort_lib.hip", "ksort_server.hip", "ksort_tune.hip", "ksort_exact.hip", "ksort_copy.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -36,10 +36,14 @@ struct Variant {
 };
 
 const std::vector<Variant>& variants();
+// What a tuned choice applies to: single arrays of about n keys, or packed
+// batches of about n keys in all.
+enum TuneKind { kTuneSingle = 0, kTuneBatch = 1 };
 // Explicit `tune` if given; otherwise the autotuned variant for inputs of
-// about n keys, else the default for the key type.
-const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n = -1);
-bool tuned_for(int dtype, int64_t n, ksort_tuning* out);
+// about n keys of that kind, else the default for the key type.
+const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n = -1, int kind = kTuneSingle,
+                            bool use_tuned = true);
+bool tuned_for(int dtype, int64_t n, int kind, ksort_tuning* out);
 int set_default_variant(int dtype, const ksort_tuning* tune);
 
 struct DeviceInfo {
@@ -137,6 +141,9 @@ int launch_clear_status(Workspace& ws);  // the look-back words only
 int launch_init(Workspace& ws, const Variant& v, const InitArgs& ia, int64_t nblocks);
 int launch_stage(Workspace& ws, const Variant& v, const StageArgs& a, int grid);
 int stage_grid(const Variant& v, const DeviceInfo& di, const Caps& c);
+
+// Polls a look-back wait makes before it gives up (KSORT_SPIN_LIMIT, or 2^22).
+uint32_t spin_limit_setting();
 
 // Predicted number of level passes for n keys (used to size launch batches).
 int predict_stages(int64_t n, int cutoff, int tile);

@@ -71,11 +71,14 @@ const std::vector<Variant>& variants() {
       make_variant<double, 512, 16, 2048>(KSORT_F64),
       make_variant<double, 1024, 8, 2048>(KSORT_F64),
       make_variant<double, 512, 16, 1024>(KSORT_F64),
+      make_variant<double, 256, 24, 2048>(KSORT_F64),
+      make_variant<double, 256, 32, 2048>(KSORT_F64),
       make_variant<float, 512, 32, 2048>(KSORT_F32),
       make_variant<float, 512, 24, 2048>(KSORT_F32),
       make_variant<float, 512, 16, 2048>(KSORT_F32),
       make_variant<float, 1024, 8, 2048>(KSORT_F32),
       make_variant<float, 512, 16, 1024>(KSORT_F32),
+      make_variant<float, 256, 32, 2048>(KSORT_F32),
   };
   return vs;
 }
@@ -93,7 +96,7 @@ static int variant_index(int dtype, int block, int items, int cutoff) {
 
 static constexpr int64_t kSmallSortKeys = 3000000;
 
-const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n) {
+const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n, int kind, bool use_tuned) {
   if (dtype != KSORT_F64 && dtype != KSORT_F32) return nullptr;
   const auto& vs = variants();
   if (tune && (tune->block || tune->items || tune->cutoff)) {
@@ -101,7 +104,7 @@ const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n) {
     return j < 0 ? nullptr : &vs[j];
   }
   ksort_tuning tn;
-  if (n >= 0 && tuned_for(dtype, n, &tn)) {
+  if (use_tuned && n >= 0 && tuned_for(dtype, n, kind, &tn)) {
     const int j = variant_index(dtype, tn.block, tn.items, tn.cutoff);
     if (j >= 0) return &vs[j];
   }
@@ -341,7 +344,7 @@ void release_workspaces() {
 // microseconds; 2^22 polls take seconds.  KSORT_SPIN_LIMIT (a decimal count)
 // overrides it, read whenever a pass is enqueued (a captured graph keeps the
 // value it was captured with); tests use a tiny limit to force the error.
-static uint32_t spin_limit_setting() {
+uint32_t spin_limit_setting() {
   constexpr uint32_t kDefault = 1u << 22;
   const char* s = getenv("KSORT_SPIN_LIMIT");
   if (!s || !*s) return kDefault;
@@ -597,7 +600,7 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
   if (n > 0 && !d_data) return fail(KSORT_EINVAL, "null data pointer");
   if (d_offsets == nullptr && nseg != 1) return fail(KSORT_EINVAL, "internal: single array needs nseg == 1");
   if (n > ((int64_t)1 << 31) - 1) return fail(KSORT_EINVAL, "more than 2^31-1 keys");
-  const Variant* v = find_variant(dtype, tune, n);
+  const Variant* v = find_variant(dtype, tune, n, d_offsets ? kTuneBatch : kTuneSingle);
   if (!v) return fail(KSORT_EINVAL, "no such kernel variant");
   if (nseg == 0) return KSORT_OK;
   if (d_offsets == nullptr && n <= 1) {
@@ -1012,9 +1015,18 @@ int64_t ksort_profile_read(ksort_level_record* out, int64_t cap) {
   return n;
 }
 
+static size_t workspace_bytes_for(const Variant* v, int64_t n, int64_t nseg);
+
 size_t ksort_workspace_bytes(int dtype, int64_t n, int64_t nseg) {
-  const Variant* v = find_variant(dtype, nullptr, n);
-  if (!v || n < 0 || nseg < 0) return 0;
+  if (n < 0 || nseg < 0) return 0;
+  // the variant a single sort or a batch of this size would take
+  const Variant* vs = find_variant(dtype, nullptr, n, kTuneSingle);
+  const Variant* vb = find_variant(dtype, nullptr, n, kTuneBatch);
+  if (!vs || !vb) return 0;
+  return std::max(workspace_bytes_for(vs, n, nseg), workspace_bytes_for(vb, n, nseg));
+}
+
+static size_t workspace_bytes_for(const Variant* v, int64_t n, int64_t nseg) {
   // the larger of the sort's and the one-level pass's lists
   Caps c = caps_for(*v, n, nseg, false);
   const Caps cl = caps_for(*v, n, nseg, true);

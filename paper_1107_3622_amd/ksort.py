@@ -81,10 +81,14 @@ SIGNATURES = {
     "ksort_get_default": (_int, [_int, _p]),
     "ksort_set_default": (_int, [_int, _p]),
     "ksort_autotune": (_int, [_int, _i64, _p, _p]),
+    "ksort_autotune_batch": (_int, [_int, _p, _i64, _p, _i64, _p, _p]),
+    "ksort_tune_file": (_int, [ctypes.c_char_p]),
+    "ksort_tune_count": (_int, []),
     "ksort_profile_enable": (_int, [_int]),
     "ksort_profile_count": (_i64, []),
     "ksort_profile_read": (_i64, [_p, _i64]),
     "ksort_workspace_bytes": (ctypes.c_size_t, [_int, _i64, _i64]),
+    "ksort_stream_copy": (_int, [_p, _p, ctypes.c_size_t, _int, _p]),
     "ksort_set_workspace": (_int, [_p, ctypes.c_size_t, _p]),
     "ksort_release_workspaces": (_int, []),
     "ksort_server_create": (_p, [ctypes.c_size_t, _int, _int]),
@@ -337,6 +341,29 @@ def ksort_autotune(dtype: int, n: int, stream=None) -> tuple[int, int, int]:
     return t.as_tuple()
 
 
+def ksort_autotune_batch(t, offsets, stream=None) -> tuple[int, int, int]:
+    """Tune the variant for packed batches like t (arrays per offsets); t is
+    left as it is."""
+    torch = _torch()
+    _check_keys(t)
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous int64 device tensor")
+    tn = Tuning()
+    _check(load().ksort_autotune_batch(_dtype_code(t), t.data_ptr(), t.numel(), offsets.data_ptr(),
+                                       offsets.numel() - 1, ctypes.byref(tn), _stream(stream)),
+           "ksort_autotune_batch")
+    return tn.as_tuple()
+
+
+def ksort_tune_file(path) -> None:
+    """Persist tuning choices in the JSON file `path` (and apply its entries)."""
+    _check(load().ksort_tune_file(None if path is None else os.fsencode(path)), "ksort_tune_file")
+
+
+def ksort_tune_count() -> int:
+    return int(load().ksort_tune_count())
+
+
 def ksort_profile_enable(on: bool) -> None:
     _check(load().ksort_profile_enable(1 if on else 0), "ksort_profile_enable")
 
@@ -347,6 +374,18 @@ def ksort_profile_read() -> list[dict]:
     arr = (LevelRecord * max(n, 1))()
     got = lib.ksort_profile_read(arr, n)
     return [arr[j].as_dict() for j in range(got)]
+
+
+def ksort_stream_copy(dst, src, grid: int = 0, stream=None) -> None:
+    """Copy src into dst (same size, device tensors) with the library's
+    streaming copy kernel, the ceiling a level pass is measured against."""
+    if not (dst.is_cuda and src.is_cuda and dst.is_contiguous() and src.is_contiguous()):
+        raise ValueError("dst and src must be contiguous device tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src differ in size")
+    _check(load().ksort_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, grid, _stream(stream)),
+           "ksort_stream_copy")
 
 
 def ksort_workspace_bytes(dtype: int, n: int, nseg: int = 1) -> int:

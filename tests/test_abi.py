@@ -92,3 +92,26 @@ def test_product_path_has_no_cpu_fallback():
             src = open(os.path.join(pkg, f)).read()
             assert "import oracle" not in src and "from oracle" not in src
             assert "np.sort" not in src and "torch.sort" not in src
+
+
+def test_tune_file_is_read_without_a_gpu(lib, tmp_path):
+    # the tuning file's entries are read on the host; lines that are not a
+    # whole entry are skipped; NULL forgets every choice
+    p = tmp_path / "tune.json"
+    p.write_text(
+        '{"version": 1, "entries": [\n'
+        '{"arch": "gfx950", "kind": "batch", "dtype": 0, "bucket": 25, "block": 512, "items": 16, '
+        '"cutoff": 1024, "ms": 1.5, "default_ms": 2.0},\n'
+        '{"arch": "gfx942", "kind": "single", "dtype": 1, "bucket": 20, "block": 512, "items": 32, '
+        '"cutoff": 2048, "ms": 0.5, "default_ms": 0.5},\n'
+        '{"arch": "gfx950", "kind": "single", "dtype": 0},\n'
+        ']}\n')
+    assert lib.ksort_tune_file(str(p).encode()) == 0
+    assert lib.ksort_tune_count() == 2
+    assert lib.ksort_tune_file(str(p).encode()) == 0  # read again: the same entries replace themselves
+    assert lib.ksort_tune_count() == 2
+    assert lib.ksort_tune_file(None) == 0
+    assert lib.ksort_tune_count() == 0
+    assert lib.ksort_tune_file(str(tmp_path / "missing.json").encode()) == 0
+    assert lib.ksort_tune_count() == 0
+    assert lib.ksort_tune_file(None) == 0
