@@ -19,7 +19,7 @@
 //
 // Everything follows from one number per position: the count of smaller
 // keys from its segment's start up to it (a segmented scan).  A level is
-//   scan_reduce / scan_blocks / scan_apply : that count, in ltp[];
+//   scan_level  : that count, in ltp[] (one pass, decoupled look-back);
 //   move_kernel : keys that shift or stay, and the q and r keys filed by rank;
 //   pair_kernel : q_k -> r_{k-1} and r_k -> q_k - 1, the call record, and the
 //                 segments of the next level (Steps 5-6).
@@ -36,10 +36,15 @@
 namespace ksort {
 namespace exact {
 
+// Waits for this wave's LDS accesses: lanes of a wave read what other lanes
+// of it wrote just before (a wave executes in step).
+#ifndef KS_LDS_WAIT
+#define KS_LDS_WAIT() asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory")
+#endif
+
 constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kSpan = kThreads * kItems;  // positions per scan block
-constexpr int kScanThreads = 1024;        // the one workgroup that scans the block totals
 constexpr int kShort = 64;                // sort mode: sides of at most this many keys finish in one wave
 constexpr int kPairGrid = 4096;           // most workgroups of move_kernel and pair_kernel
 constexpr int kSmallGrid = 1024;          // workgroups of small_kernel
@@ -57,10 +62,11 @@ struct LevelArgs {
   int32_t* rpos;           // position of r_k, at segment start + k
   T* qkey;
   T* rkey;
-  uint8_t* fl;             // per position: bit 0 starts a run, bit 1 a smaller key (nblocks * kSpan)
-  int32_t* bflag;          // per scan block: a segment starts in it
-  int32_t* bsum;           // per scan block: smaller keys after its last segment start
-  int32_t* carry;          // per scan block: smaller keys carried into its first position
+  uint64_t* sstat[2];      // per scan block, by level parity: its published run (look-back word)
+  int32_t* sctr;           // two ticket counters, by level parity
+  int32_t* err;            // set when a look-back wait gives up
+  int32_t par;             // this level's parity
+  uint32_t spin_limit;     // polls of a look-back wait before it gives up
   int64_t n;
   int32_t nblocks;
   int32_t sort_mode;       // 1: whole-array sort (final keys copied, next level built)
@@ -129,26 +135,54 @@ __device__ Run block_scan(Run r, int* sf, int* ss) {
   return r;
 }
 
-// Each thread takes kItems consecutive positions; their flags are kept as one
-// 16-byte word for scan_apply.
-static_assert(kItems == 16, "one 16-byte flag word per thread");
+// Look-back word of a scan block: the smaller-key count in bits 0..31, the
+// run flag (a segment starts in the block) in bit 32, and in bits 33..34
+// what the word holds: 1 the block's own run, 2 the run from the array's
+// start through the block.  0 means not yet published; each level clears the
+// words of the level after it.
+constexpr uint64_t kRunOwn = 1, kRunIncl = 2;
+__device__ __forceinline__ uint64_t run_word(uint64_t kind, Run r) {
+  return (kind << 33) | ((uint64_t)(r.f & 1) << 32) | (uint32_t)r.s;
+}
+__device__ __forceinline__ Run word_run(uint64_t w) { return Run{(int)((w >> 32) & 1), (int)(uint32_t)w}; }
 
+// The count of smaller keys from each position's segment start through it,
+// in one pass: each workgroup takes the next scan block in claim order (so
+// every block it waits for belongs to a workgroup that has started), scans
+// its kItems x kThreads positions, publishes its run, and finds the run
+// carried into it by decoupled look-back: the nearest earlier block that has
+// published its run from the array's start, or that contains a segment start,
+// ends the look-back.  The first workgroup of a level also clears the
+// level's counters (active positions, filed sides) and the next level's
+// ticket counter.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void scan_reduce(LevelArgs<T> a) {
+__global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
   __shared__ int sf[kThreads], ss[kThreads];
+  __shared__ int s_b, s_pf, s_ps;
+  if (threadIdx.x == 0) {
+    const int b = atomicAdd(a.sctr + a.par, 1);
+    s_b = b;
+    if (b == 0) {
+      a.sctr[a.par ^ 1] = 0;
+      if (a.active) *a.active = 0;
+      if (a.nsmall) *a.nsmall = 0;
+    }
+  }
+  __syncthreads();
+  const int64_t blk = s_b;
+  uint64_t* st = a.sstat[a.par];
+  if (threadIdx.x == 0) a.sstat[a.par ^ 1][blk] = 0;  // the next level's word starts unpublished
   if (a.act) {
-    if (threadIdx.x == 0) a.act_next[blockIdx.x] = 0;
-    if (!a.act[blockIdx.x]) {  // every position final: a run start that counts nothing
-      if (threadIdx.x == 0) {
-        a.bflag[blockIdx.x] = 1;
-        a.bsum[blockIdx.x] = 0;
-      }
+    if (threadIdx.x == 0) a.act_next[blk] = 0;
+    if (!a.act[blk]) {  // every position final: a run start that counts nothing
+      if (threadIdx.x == 0) __hip_atomic_store(st + blk, run_word(kRunIncl, Run{1, 0}), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
   }
-  const int64_t base = (int64_t)blockIdx.x * kSpan + (int64_t)threadIdx.x * kItems;
+  const int64_t base = blk * kSpan + (int64_t)threadIdx.x * kItems;
+  uint32_t fbits = 0, lbits = 0;  // per item: run start, smaller key
   Run r{0, 0};
-  uint32_t w[4] = {0, 0, 0, 0};
   if (base + kItems <= a.n) {
     int32_t h[kItems];
     T v[kItems];
@@ -162,71 +196,78 @@ __global__ __launch_bounds__(kThreads) void scan_reduce(LevelArgs<T> a) {
       const bool start = h[j] < 0 || h[j] == base + j;
       const bool lt = !start && !(a.cur[h[j]] <= v[j]);
       r = join(r, Run{start ? 1 : 0, lt ? 1 : 0});
-      w[j / 4] |= (uint32_t)((start ? 1 : 0) | (lt ? 2 : 0)) << (8 * (j % 4));
+      fbits |= (uint32_t)start << j;
+      lbits |= (uint32_t)lt << j;
     }
   } else {
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const Run p = pos_run(a, base + j);
       r = join(r, p);
-      w[j / 4] |= (uint32_t)(p.f | (p.s << 1)) << (8 * (j % 4));
+      fbits |= (uint32_t)p.f << j;
+      lbits |= (uint32_t)p.s << j;
     }
   }
-  *(uint4*)(a.fl + base) = make_uint4(w[0], w[1], w[2], w[3]);
-  r = block_scan<kThreads>(r, sf, ss);
-  if (threadIdx.x == kThreads - 1) {
-    a.bflag[blockIdx.x] = r.f;
-    a.bsum[blockIdx.x] = r.s;
-  }
-}
-
-// One workgroup: the run carried into each scan block.  It also clears the
-// level's counters (active positions, filed sides) before move_kernel and
-// pair_kernel use them.
-template <typename T>
-__global__ __launch_bounds__(kScanThreads) void scan_blocks(LevelArgs<T> a) {
-  __shared__ int sf[kScanThreads], ss[kScanThreads];
-  if (threadIdx.x == 0) {
-    if (a.active) *a.active = 0;
-    if (a.nsmall) *a.nsmall = 0;
-  }
-  const int nb = a.nblocks;
-  const int per = (nb + kScanThreads - 1) / kScanThreads;
-  const int b0 = threadIdx.x * per;
-  Run r{0, 0};
-  for (int b = b0; b < min(nb, b0 + per); ++b) r = join(r, Run{a.bflag[b], a.bsum[b]});
-  const Run inc = block_scan<kScanThreads>(r, sf, ss);
-  Run run = threadIdx.x > 0 ? Run{sf[threadIdx.x - 1], ss[threadIdx.x - 1]} : Run{0, 0};
-  for (int b = b0; b < min(nb, b0 + per); ++b) {
-    a.carry[b] = run.s;
-    run = join(run, Run{a.bflag[b], a.bsum[b]});
-  }
-  (void)inc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void scan_apply(LevelArgs<T> a) {
-  __shared__ int sf[kThreads], ss[kThreads];
-  if (a.act && !a.act[blockIdx.x]) return;  // counts are read only inside segments
-  const int64_t base = (int64_t)blockIdx.x * kSpan + (int64_t)threadIdx.x * kItems;
-  const uint4 wv = *(const uint4*)(a.fl + base);
-  const uint32_t w[4] = {wv.x, wv.y, wv.z, wv.w};
-  Run rs[kItems];
-  Run r{0, 0};
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    const uint32_t b = (w[j / 4] >> (8 * (j % 4))) & 3u;
-    rs[j] = Run{(int)(b & 1u), (int)(b >> 1)};
-    r = join(r, rs[j]);
-  }
   const Run inc = block_scan<kThreads>(r, sf, ss);
-  Run run = join(Run{0, a.carry[blockIdx.x]},
-                 threadIdx.x > 0 ? Run{sf[threadIdx.x - 1], ss[threadIdx.x - 1]} : Run{0, 0});
+  // the run carried into this block
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const Run agg{sf[kThreads - 1], ss[kThreads - 1]};
+    Run pre{0, 0};
+    if (blk == 0) {
+      if (lane == 0) __hip_atomic_store(st, run_word(kRunIncl, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (lane == 0) __hip_atomic_store(st + blk, run_word(kRunOwn, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int64_t top = blk - 1;  // lane j watches block top - j
+      int sum = 0;
+      uint32_t polls = 0;
+      for (;;) {
+        const int64_t j = top - lane;
+        uint64_t w = j >= 0 ? __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        // wait until every watched block has published
+        while (__ballot(j >= 0 && (w >> 33) == 0)) {
+          if (++polls > a.spin_limit) break;
+          __builtin_amdgcn_s_sleep(1);
+          if (j >= 0 && (w >> 33) == 0) w = __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (polls > a.spin_limit) {
+          if (lane == 0) atomicExch(a.err, 1);
+          pre = Run{1, 0};
+          break;
+        }
+        // the nearest block whose word ends the look-back: a run from the
+        // array's start, or a run with a segment start in it
+        const bool stop = j >= 0 && ((w >> 33) == kRunIncl || ((w >> 32) & 1));
+        const uint64_t sm = __ballot(stop);
+        const int first = sm ? __builtin_ctzll(sm) : 64;
+        const Run wr = word_run(w);
+        int part = j >= 0 && lane < first ? wr.s : 0;
+        for (int d = 32; d > 0; d >>= 1) part += __shfl_xor(part, d);
+        sum += part;
+        if (sm) {
+          const uint64_t ws = __shfl(w, first);
+          const Run rs = word_run(ws);
+          pre = Run{rs.f, rs.s + sum};
+          break;
+        }
+        top -= 64;
+      }
+      if (lane == 0) {
+        __hip_atomic_store(st + blk, run_word(kRunIncl, join(pre, agg)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (lane == 0) {
+      s_pf = pre.f;
+      s_ps = pre.s;
+    }
+  }
+  __syncthreads();
+  Run run = join(Run{s_pf, s_ps}, threadIdx.x > 0 ? Run{sf[threadIdx.x - 1], ss[threadIdx.x - 1]} : Run{0, 0});
   (void)inc;
   int32_t out[kItems];
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
-    run = join(run, rs[j]);
+    run = join(run, Run{(int)((fbits >> j) & 1), (int)((lbits >> j) & 1)});
     out[j] = run.s;
   }
   if (base + kItems <= a.n) {
@@ -458,7 +499,7 @@ __global__ __launch_bounds__(kThreads) void small_kernel(LevelArgs<T> a) {
           rs[w][s + (c - lp + 1)] = lane;  // r, by rank from the right in (m, right]
         }
       }
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      KS_LDS_WAIT();
       int dest = lane;
       if (act) {
         const int kq = (lane - s) - lp;
@@ -482,9 +523,9 @@ __global__ __launch_bounds__(kThreads) void small_kernel(LevelArgs<T> a) {
         }
       }
       vs[w][dest] = v;
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      KS_LDS_WAIT();
       v = vs[w][lane < kShort ? lane : 0];
-      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // all reads done before the next level's writes
+      KS_LDS_WAIT();  // all reads done before the next level's writes
       if (act) {
         if (lane < i) {
           len = c >= 2 ? c : 0;
@@ -584,10 +625,11 @@ static int alloc_level(Buffers& B, LevelArgs<T>& a, int64_t n, bool sort_mode, i
   hd[1] = ln[1] = nullptr;
   if ((rc = B.take(&hd[0], (size_t)n)) || (rc = B.take(&ln[0], (size_t)n)) || (rc = B.take(&a.ltp, (size_t)n)) ||
       (rc = B.take(&a.qpos, (size_t)n)) || (rc = B.take(&a.rpos, (size_t)n)) || (rc = B.take(&a.qkey, (size_t)n)) ||
-      (rc = B.take(&a.rkey, (size_t)n)) || (rc = B.take(&a.fl, (size_t)nb * kSpan)) ||
-      (rc = B.take(&a.bflag, (size_t)nb)) || (rc = B.take(&a.bsum, (size_t)nb)) ||
-      (rc = B.take(&a.carry, (size_t)nb)))
+      (rc = B.take(&a.rkey, (size_t)n)) || (rc = B.take(&a.sstat[0], (size_t)2 * nb)) ||
+      (rc = B.take(&a.sctr, 2)) || (rc = B.take(&a.err, 1)))
     return rc;
+  a.sstat[1] = a.sstat[0] + nb;
+  a.spin_limit = spin_limit_setting();
   if (sort_mode) {
     if ((rc = B.take(&hd[1], (size_t)n)) || (rc = B.take(&ln[1], (size_t)n)) || (rc = B.take(&a.active, 1))) return rc;
   }
@@ -598,15 +640,22 @@ static int alloc_level(Buffers& B, LevelArgs<T>& a, int64_t n, bool sort_mode, i
   return KSORT_OK;
 }
 
+// Clears the look-back words, ticket counters and error flag of a run.
+template <typename T>
+static int clear_scan_state(const LevelArgs<T>& a, hipStream_t st) {
+  KSORT_HIP(hipMemsetAsync(a.sstat[0], 0, (size_t)2 * a.nblocks * sizeof(uint64_t), st));
+  KSORT_HIP(hipMemsetAsync(a.sctr, 0, 2 * sizeof(int32_t), st));
+  KSORT_HIP(hipMemsetAsync(a.err, 0, sizeof(int32_t), st));
+  return KSORT_OK;
+}
+
 template <typename T>
 static int launch_level(const LevelArgs<T>& a, hipStream_t st) {
   const int nb = a.nblocks;
-  scan_reduce<T><<<nb, kThreads, 0, st>>>(a);
-  scan_blocks<T><<<1, kScanThreads, 0, st>>>(a);
-  scan_apply<T><<<nb, kThreads, 0, st>>>(a);
-  move_kernel<T><<<grid_for(a.n), kThreads, 0, st>>>(a);
-  pair_kernel<T><<<grid_for(a.n), kThreads, 0, st>>>(a);
-  if (a.small) small_kernel<T><<<kSmallGrid, kThreads, 0, st>>>(a);
+  hipLaunchKernelGGL(scan_level<T>, dim3(nb), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(move_kernel<T>, dim3(grid_for(a.n)), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(pair_kernel<T>, dim3(grid_for(a.n)), dim3(kThreads), 0, st, a);
+  if (a.small) hipLaunchKernelGGL(small_kernel<T>, dim3(kSmallGrid), dim3(kThreads), 0, st, a);
   KSORT_HIP(hipGetLastError());
   return KSORT_OK;
 }
@@ -621,8 +670,6 @@ static int check_device() {
   return KSORT_OK;
 }
 
-// The number of scan blocks one workgroup totals in scan_blocks is bounded
-// by its per-thread loop, not by a fixed array: any n below 2^31 works.
 template <typename T>
 static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_calls, int64_t calls_cap,
                       int64_t* d_ncalls, hipStream_t st) {
@@ -643,7 +690,7 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
   T* scratch = nullptr;
   if ((rc = B.take(&scratch, (size_t)n))) return rc;
   unsigned long long* h_active = nullptr;
-  KSORT_HIP(hipHostMalloc((void**)&h_active, sizeof(unsigned long long), hipHostMallocDefault));
+  KSORT_HIP(hipHostMalloc((void**)&h_active, 2 * sizeof(unsigned long long), hipHostMallocDefault));
   struct HostFree {
     void* p;
     ~HostFree() { (void)hipHostFree(p); }
@@ -661,7 +708,8 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
     if ((rc = B.take(&a.wcalls, (size_t)(kPairGrid + kSmallGrid)))) return rc;
     KSORT_HIP(hipMemsetAsync(a.wcalls, 0, (size_t)(kPairGrid + kSmallGrid) * sizeof(unsigned long long), st));
   }
-  init_whole<<<grid_for(n), kThreads, 0, st>>>(H[0], Ln[0], n);
+  if ((rc = clear_scan_state<T>(a, st))) return rc;
+  hipLaunchKernelGGL(init_whole, dim3(grid_for(n)), dim3(kThreads), 0, st, H[0], Ln[0], n);
   KSORT_HIP(hipGetLastError());
   T* bufs[2] = {data, scratch};
   int cur = 0;
@@ -684,16 +732,19 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
       a.act_prev = act_ring + (size_t)((level + 2) % 3) * a.nblocks;
       a.act_next = act_ring + (size_t)((level + 1) % 3) * a.nblocks;
       a.first_pivot = level == 0 ? d_first_pivot : nullptr;
+      a.par = (int32_t)(level & 1);
       if ((rc = launch_level<T>(a, st))) return rc;
       cur ^= 1;
     }
     KSORT_HIP(hipMemcpyAsync(h_active, a.active, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    KSORT_HIP(hipMemcpyAsync(h_active + 1, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     KSORT_HIP(hipStreamSynchronize(st));
+    if (((const int32_t*)(h_active + 1))[0] != 0) return fail(KSORT_EINTERNAL, "a look-back wait timed out");
     if (*h_active == 0) break;
   }
   if (cur == 1) KSORT_HIP(hipMemcpyAsync(data, scratch, (size_t)n * sizeof(T), hipMemcpyDeviceToDevice, st));
   if (a.wcalls) {
-    sum_calls<<<1, kThreads, 0, st>>>(a.wcalls, kPairGrid + kSmallGrid, a.ncalls);
+    hipLaunchKernelGGL(sum_calls, dim3(1), dim3(kThreads), 0, st, a.wcalls, kPairGrid + kSmallGrid, a.ncalls);
     KSORT_HIP(hipGetLastError());
   }
   KSORT_HIP(hipStreamSynchronize(st));
@@ -742,16 +793,21 @@ static int level_exact(const T* d_in, T* d_out, int64_t n, const int64_t* d_left
   KSORT_HIP(hipMemcpyAsync(dclen, clen.data(), clen.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
   KSORT_HIP(hipMemcpyAsync(dcs, cs.data(), cs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
   KSORT_HIP(hipMemcpyAsync(dok, ok.data(), ok.size(), hipMemcpyHostToDevice, st));
-  fill_i32<<<grid_for(n), kThreads, 0, st>>>(H[0], n, -1);
-  if (!cl.empty()) mark_segments<<<(unsigned)cl.size(), kThreads, 0, st>>>(H[0], Ln[0], dcl, dclen, dcs);
+  hipLaunchKernelGGL(fill_i32, dim3(grid_for(n)), dim3(kThreads), 0, st, H[0], n, -1);
+  if (!cl.empty()) hipLaunchKernelGGL(mark_segments, dim3((unsigned)cl.size()), dim3(kThreads), 0, st, H[0], Ln[0], dcl, dclen, dcs);
   KSORT_HIP(hipGetLastError());
   a.cur = d_in;
   a.nxt = d_out;
   a.sort_mode = 0;
+  a.par = 0;
+  if ((rc = clear_scan_state<T>(a, st))) return rc;
   if ((rc = launch_level<T>(a, st))) return rc;
-  gather_pivots<<<grid_for(nseg), kThreads, 0, st>>>(a.piv_at, d_left, dok, nseg, d_pivot);
+  hipLaunchKernelGGL(gather_pivots, dim3(grid_for(nseg)), dim3(kThreads), 0, st, a.piv_at, d_left, dok, nseg, d_pivot);
   KSORT_HIP(hipGetLastError());
+  int32_t h_err = 0;
+  KSORT_HIP(hipMemcpyAsync(&h_err, a.err, sizeof h_err, hipMemcpyDeviceToHost, st));
   KSORT_HIP(hipStreamSynchronize(st));
+  if (h_err) return fail(KSORT_EINTERNAL, "a look-back wait timed out");
   if (bad) return fail(KSORT_EINVAL, "a segment is outside [0, n) or has len < 1");
   return KSORT_OK;
 }

@@ -114,6 +114,16 @@ ksim_dims* ksim_cur();
 #define gridDim (ksim_cur()->gdim)
 
 void __syncthreads();
+// 1 if any thread of the workgroup passes a nonzero value (a barrier)
+inline int __syncthreads_or(int p) {
+  static thread_local int acc;
+  __syncthreads();  // every thread has read the previous result
+  if (ksim_cur()->tid.x == 0) acc = 0;
+  __syncthreads();
+  if (p) acc = 1;
+  __syncthreads();
+  return acc;
+}
 void ksim_yield();
 uint64_t ksim_ballot(bool pred);
 uint32_t ksim_lane();
@@ -122,7 +132,25 @@ uint64_t ksim_readlane(uint64_t v, int src);
 uint64_t ksim_readfirstlane(uint64_t v);
 int ksim_dpp(int old, int v, int ctrl, int row_mask, int bank_mask, bool bound_ctrl);
 
+// value of lane `src` (its own choice per lane) of the wave (a collective)
+uint64_t ksim_shfl(uint64_t v, int src);
+
 inline uint64_t __ballot(int pred) { return ksim_ballot(pred != 0); }
+template <typename T>
+inline T __shfl(T v, int src, int width = 64) {
+  static_assert(sizeof(T) <= 8, "__shfl of a value wider than 8 bytes");
+  uint64_t b = 0;
+  memcpy(&b, &v, sizeof(T));
+  const int base = (int)ksim_lane() / width * width;
+  b = ksim_shfl(b, base + ((src % width) + width) % width);
+  T r;
+  memcpy(&r, &b, sizeof(T));
+  return r;
+}
+template <typename T>
+inline T __shfl_xor(T v, int mask, int width = 64) {
+  return __shfl(v, (int)ksim_lane() ^ mask, width);
+}
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 #define __builtin_amdgcn_readfirstlane(v) ((int)ksim_readfirstlane((uint64_t)(uint32_t)(v)))
 #define __builtin_amdgcn_readlane(v, j) ((int)ksim_readlane((uint64_t)(uint32_t)(v), (j)))
@@ -159,6 +187,7 @@ inline long long min(long long a, long long b) { return a < b ? a : b; }
 inline long long max(long long a, long long b) { return a > b ? a : b; }
 inline long min(long a, long b) { return a < b ? a : b; }
 inline long max(long a, long b) { return a > b ? a : b; }
+inline int atomicExch(int* p, int v) { return __atomic_exchange_n(p, v, __ATOMIC_SEQ_CST); }
 inline int atomicCAS(int* p, int cmp, int v) {
   __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
   return cmp;
@@ -169,6 +198,15 @@ inline int atomicMax(int* p, int v) {
   }
   return old;
 }
+
+struct int2 {
+  int x, y;
+};
+struct alignas(16) int4 {
+  int x, y, z, w;
+};
+inline int2 make_int2(int x, int y) { return int2{x, y}; }
+inline int4 make_int4(int x, int y, int z, int w) { return int4{x, y, z, w}; }
 
 inline float __int_as_float(int x) {
   float f;

@@ -496,7 +496,7 @@ void __syncthreads() {
 
 namespace {
 
-enum { kBallot = 1, kReadlane, kFirst, kDpp, kSync };
+enum { kBallot = 1, kReadlane, kFirst, kDpp, kSync, kShfl };
 
 // All live lanes of the calling wave deposit v; returns the wave's values
 // (and, in *mask, the lanes that deposited) once everyone has.
@@ -548,6 +548,14 @@ uint64_t ksim_readlane(uint64_t x, int src) {
   uint64_t m;
   const uint64_t* v = collect(x, kReadlane, &m);
   if (src < 0 || src >= kWave || !((m >> src) & 1)) die("readlane of an inactive lane");
+  return v[src];
+}
+
+uint64_t ksim_shfl(uint64_t x, int src) {
+  if (!t_blk) return x;
+  uint64_t m;
+  const uint64_t* v = collect(x, kShfl, &m);
+  if (src < 0 || src >= kWave || !((m >> src) & 1)) die("shuffle from an inactive lane");
   return v[src];
 }
 

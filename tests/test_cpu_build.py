@@ -9,7 +9,10 @@ thread and keeps guard pages around every device allocation.
   of mixed sizes and key types, 256 in flight;
 * the same with asynchronous in-order queues shared by several streams
   (a producer and a checker stream beside the server's), with and without
-  kernels of those streams competing for the workgroup slots of the device.
+  kernels of those streams competing for the workgroup slots of the device;
+* the literal arrangement (one level on many segments, and the whole sort
+  with its call records) against the C oracle, which only this test program
+  links, at sizes whose look-back spans more than one window of 64 blocks.
 """
 import os
 import subprocess
@@ -19,20 +22,26 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1107_3622_amd", "csrc")
 SIM = os.path.join(ROOT, "tests", "cpu_sim")
-LIB_SOURCES = [os.path.join(CSRC, f) for f in ("ksort_lib.hip", "ksort_server.hip", "ksort_tune.hip")]
+LIB_SOURCES = [os.path.join(CSRC, f) for f in ("ksort_lib.hip", "ksort_server.hip", "ksort_tune.hip",
+                                                 "ksort_exact.hip")]
+ORACLE = os.path.join(ROOT, "oracle")
 
 
 @pytest.fixture(scope="module")
 def sim_build(tmp_path_factory):
     out = tmp_path_factory.mktemp("ksim")
+    oracle_obj = str(out / "ksort_oracle.o")
+    subprocess.run(["gcc", "-O1", "-g", "-c", os.path.join(ORACLE, "ksort_oracle.c"), "-I", ORACLE, "-o", oracle_obj],
+                   check=True)
     exes = {}
-    for drv in ("plain_sim", "server_sim", "serve_async_sim"):
+    for drv in ("plain_sim", "server_sim", "serve_async_sim", "exact_sim"):
         exe = out / drv
+        extra = [oracle_obj] if drv == "exact_sim" else []
         subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-rdynamic", "-Wall",
-                        "-Wno-attributes", "-Wno-unknown-pragmas", "-Wno-unused-function",
-                        "-I", SIM, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                        "-Wno-attributes", "-Wno-unknown-pragmas", "-Wno-unused-function", "-Wno-sign-compare",
+                        "-I", SIM, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", ORACLE,
                         "-x", "c++", *LIB_SOURCES, "-x", "none", os.path.join(SIM, "ksim.cpp"),
-                        os.path.join(SIM, drv + ".cpp"), "-o", str(exe), "-lpthread"], check=True)
+                        os.path.join(SIM, drv + ".cpp"), *extra, "-o", str(exe), "-lpthread"], check=True)
         exes[drv] = str(exe)
     return exes
 
@@ -61,3 +70,9 @@ def test_server_with_async_queues_on_the_host_build(sim_build, hwq, slots):
         env["KSIM_SLOTS"] = str(slots)
     out = run(sim_build["serve_async_sim"], [120, 1000, 20000, 256, 1024, 2000], env)
     assert "120 completed, 0 failed" in out and "0 wrong" in out
+
+
+@pytest.mark.parametrize("n,kinds", [(300, "01234"), (2000, "01"), (300_000, "0")])
+def test_exact_arrangement_on_the_host_build(sim_build, n, kinds):
+    out = run(sim_build["exact_sim"], [n, kinds], {})
+    assert "MISMATCH" not in out and "0 failed" in out
