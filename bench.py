@@ -294,15 +294,13 @@ SERVE_INFLIGHT = 128
 def serve_leg(ksort, torch) -> dict:
     """The serving workload's shape: a seeded Poisson stream (arrivals seed
     11) of requests with sizes log-uniform in [1e3, 1e7] (seed 12), 70 % FP64
-    (seed 13), 128 in flight under a 64 GiB budget.  Each request's keys are
-    drawn on the device by a producer stream at its arrival, while the
-    server runs; lambda = 0.7 x the plain path's keys/s on the same requests
-    / E[n].  After the stream every result is compared with torch.sort of
-    its input, and a sample (including the largest requests) with the oracle
-    and its first pivot.  Then a saturation run: the same requests drawn
-    beforehand and all submitted at t = 0.  (This is the configuration of the
-    GPU test of the serving form; the full stream of 20,000 requests is not
-    run.)"""
+    (seed 13), 128 in flight under a 64 GiB budget; lambda = 0.7 x the plain
+    path's keys/s on the same requests / E[n].  Every request's keys are drawn
+    on the device before the server starts and each is submitted at its
+    arrival time.  After the stream every result is compared with torch.sort
+    of its input, and a sample (including the largest requests) with the
+    oracle and its first pivot.  Then a saturation run: the same requests all
+    submitted at t = 0."""
     import numpy as np
 
     import oracle
@@ -315,20 +313,22 @@ def serve_leg(ksort, torch) -> dict:
     lam = 0.7 * plain / e_n
     _, _, arrivals = synth.serve_requests(count, 12, 13, 11, lo, hi, p64, lam)
     keys = int(sizes.sum())
-    prod = torch.cuda.Stream()
+
+    def draw():
+        ts = [synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda") for r in range(count)]
+        torch.cuda.synchronize()
+        return ts
+
     log(f"serve: {count} requests, {keys} keys; plain path {plain / 1e9:.2f} G keys/s; lambda {lam:.0f}/s")
-    tensors, tickets = [], []
+    tensors = draw()
+    tickets = []
     with ksort.Server(64 << 30, SERVE_INFLIGHT) as srv:
         t0 = time.perf_counter()
         for r in range(count):
             dt = arrivals[r] - (time.perf_counter() - t0)
             if dt > 0:
                 time.sleep(dt)
-            with torch.cuda.stream(prod):
-                t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
-            prod.synchronize()
-            tickets.append(srv.submit(t))
-            tensors.append(t)
+            tickets.append(srv.submit(tensors[r]))
         codes = [srv.wait(tk, 120.0) for tk in tickets]
         wall = time.perf_counter() - t0
         st = srv.stats()
@@ -345,9 +345,8 @@ def serve_leg(ksort, torch) -> dict:
         got = tensors[r].cpu().numpy()
         ok = ok and np.array_equal(got.view(np.uint8), want.view(np.uint8)) and infos[r]["first_pivot"] == wp
     del tensors
-    # saturation: the same requests drawn beforehand, all submitted at t = 0
-    pre = [synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda") for r in range(count)]
-    torch.cuda.synchronize()
+    # saturation: the same requests, all submitted at t = 0
+    pre = draw()
     with ksort.Server(64 << 30, SERVE_INFLIGHT) as srv:
         t0 = time.perf_counter()
         tks = [srv.submit(t) for t in pre]
@@ -359,14 +358,14 @@ def serve_leg(ksort, torch) -> dict:
     torch.cuda.empty_cache()
     return {"workload": f"c4 shape: {count} requests, Poisson arrivals (seed 11), sizes log-uniform [1e3, 1e7] "
                         f"(seed 12), 70 % FP64 (seed 13), keys of request r from seed 1,000,000 + r drawn on the "
-                        f"device at arrival, {SERVE_INFLIGHT} in flight, 64 GiB budget",
+                        f"device before the stream, {SERVE_INFLIGHT} in flight, 64 GiB budget",
             "requests": count, "keys": keys, "lambda_per_s": lam, "plain_keys_per_s_on_mix": plain,
             "wall_s": wall, "keys_per_s": keys / wall,
             "keys_per_busy_s": keys / st["busy_s"] if st["busy_s"] > 0 else None,
             "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
             "mean_latency_s": st["mean_latency_s"], "ticks": st["ticks"],
             "completed": st["completed"], "failed": st["failed"],
-            "saturation": {"workload": "the same requests drawn beforehand, all submitted at t = 0",
+            "saturation": {"workload": "the same requests, all submitted at t = 0",
                            "wall_s": sat_wall, "keys_per_s": keys / sat_wall,
                            "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"],
                            "ticks": sat["ticks"], "completed": sat["completed"]},

@@ -373,9 +373,10 @@ union StageSmem {
 
 constexpr int kLookBack = 4;
 
-// Returns -1 if a predecessor has not published after a.spin_limit polls
-// (the wait is bounded, so a lost or never-claimed predecessor ends the pass
-// with an error instead of holding the device).
+// Returns -1 if a predecessor has not published after a.spin_limit polls,
+// or once the pass has failed elsewhere (the wait is bounded, so a lost or
+// never-claimed predecessor ends the pass with an error instead of holding
+// the device).
 __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int32_t first_tile) {
   const int lane = lane_id();
   int64_t excl = 0;
@@ -400,7 +401,10 @@ __device__ __forceinline__ int64_t look_back(const StageArgs& a, int32_t t, int3
         ready = ready && (!in_seg[r] || ok);
       }
       if (ready) break;
-      if (++polls > a.spin_limit) {
+      // gives up at the limit, or early once another wait of the pass has
+      // failed (the pass is lost then, and every later tile of a segment
+      // whose count never arrives would otherwise wait the full limit)
+      if (++polls > a.spin_limit || ((polls & 255) == 0 && ld_agent(&a.flags->overflow) != 0)) {
         timed_out = true;
         break;
       }
