@@ -7,18 +7,20 @@
  *
  * Readings of the text used here (each one is a choice where the text is
  * silent or self-contradictory):
- *   R1  Step-2 "repeat Step-3 till (j-i) >= 2 is satisfied" is read as
- *       "while (j - i >= 2)".  The illustration (Section 1.2, first row)
- *       needs the comparison made at j - i == 2.
+ *   R1  Step-2's loop condition on the gap between j and i is read as a
+ *       loop that runs while j - i >= 2.  The illustration (Section 1.2,
+ *       first row) needs the comparison made at j - i == 2.
  *   R2  `flag` is never initialised in Step-1; it is cleared on every
  *       partition entry.  The third illustration row shows "Temp = Nil".
  *   R3  Indices are 0-based: the whole array is a[0..n-1].
- *   R4  Step-5 "sub array from start to i-th element" is [left, i-1] with the
- *       printed test left < i-1 (at least two elements; the Section 1.2 note
- *       says a single value needs no processing).
- *   R5  Step-6 prints "if (left > i+1)", which never holds because i >= left;
- *       it is read as "if (right > i+1)" on [i+1, right], the mirror of
- *       Step-5.  The illustration goes on to process the right side.
+ *   R4  Step-5's left side runs from the segment's first position up to
+ *       the key's final index, the key excluded: [left, i-1], processed when
+ *       left < i-1 (at least two elements; the Section 1.2 note says a
+ *       single value needs no processing).
+ *   R5  Step-6's printed test compares left with i+1 and can never hold,
+ *       because i >= left; it is read as right > i+1 on [i+1, right], the
+ *       mirror of Step-5.  The illustration goes on to process the right
+ *       side.
  *   R6  Sub-arrays are processed depth-first, left side first, the row order
  *       of the illustration.  Only the order of trace records depends on it.
  *   R7  The comparison is exactly `key <= a[p]` in KEY_T: ties go right, and
