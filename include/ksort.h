@@ -160,8 +160,9 @@ KSORT_API int ksort_partition_level(int dtype, const void *d_in, void *d_out, in
  *   Overlapping segments are rejected with KSORT_EINVAL (nothing is
  *   written); invalid segments are skipped as in ksort_partition_level.
  *   n < 2^31.  The segment arrays are read back to the host and the call
- *   synchronizes the stream; device scratch of about 25n + 2n *
- *   sizeof(key) bytes is allocated and freed inside the call.
+ *   synchronizes the stream.  Device scratch of about 25n + 2n *
+ *   sizeof(key) bytes is kept per (device, stream) between calls and grown
+ *   when a call needs more; ksort_release_workspaces frees it.
  *
  * ksort_sort_exact: Steps 1-6 on d_data[0..n-1], in place, every partition
  *   call leaving the literal arrangement, so every call (its segment, key
@@ -178,9 +179,9 @@ KSORT_API int ksort_partition_level(int dtype, const void *d_in, void *d_out, in
  *                   the total number of calls (may exceed calls_cap).
  *   The call synchronizes the stream once per eight levels (the level count
  *   is the recursion depth down to sides of 64 keys, which one wave each
- *   finishes: about 2 log2 n on random keys, about n on sorted input) and
- *   allocates about 33n + 3n * sizeof(key) bytes of device scratch for its
- *   duration.  n < 2^31.
+ *   finishes: about 2 log2 n on random keys, about n on sorted input).  Its
+ *   device scratch, about 33n + 3n * sizeof(key) bytes, is kept per
+ *   (device, stream) as for ksort_partition_level_exact.  n < 2^31.
  * Errors: KSORT_EINVAL (bad dtype, n < 0 or >= 2^31, null data with n > 0,
  * d_calls without d_ncalls), KSORT_ENOMEM, KSORT_EHIP, KSORT_EUNSUPPORTED. */
 KSORT_API int ksort_partition_level_exact(int dtype, const void *d_in, void *d_out, int64_t n,
@@ -317,9 +318,10 @@ KSORT_API int ksort_set_workspace(void *d_ws, size_t bytes, void *stream);
 #define KSORT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
 KSORT_API int ksort_sort_static(int dtype, void *d_data, int64_t n, int64_t *d_first_pivot, void *stream);
 
-/* Releases every cached workspace of the calling process (all devices).
- * Memory given with ksort_set_workspace is not freed (it is the caller's);
- * the streams go back to library-owned memory. */
+/* Releases every cached workspace of the calling process (all devices),
+ * the scratch of the literal-arrangement calls included.  Memory given with
+ * ksort_set_workspace is not freed (it is the caller's); the streams go back
+ * to library-owned memory. */
 KSORT_API int ksort_release_workspaces(void);
 
 /* ------------------------------------------------------------------------

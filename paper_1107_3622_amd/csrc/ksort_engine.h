@@ -105,6 +105,7 @@ struct Workspace {
 
 Workspace* workspace_for(int device, hipStream_t stream);
 void release_workspaces();
+void release_exact_arenas();  // scratch of the literal-arrangement calls
 
 // Arguments of one stage launch built from a workspace.
 StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_out, int pivot_relative,

@@ -29,6 +29,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "ksort_engine.h"
@@ -146,79 +149,118 @@ __device__ __forceinline__ uint64_t run_word(uint64_t kind, Run r) {
 }
 __device__ __forceinline__ Run word_run(uint64_t w) { return Run{(int)((w >> 32) & 1), (int)(uint32_t)w}; }
 
+// Scan blocks a workgroup takes with one ticket.  One ticket per block cost
+// about 15 ns of serialized device-scope atomics each (24 us per level at
+// 7e6 keys, also in levels that are nearly idle).
+constexpr int kScanChunk = 4;
+
+// Inclusive scan of K Run pairs per thread across the workgroup, each of
+// the K sequences on its own (Hillis-Steele in LDS, all K in every step).
+template <int K>
+__device__ void block_scan_k(Run (&r)[K], int (*sf)[kThreads], int (*ss)[kThreads]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    sf[k][t] = r[k].f;
+    ss[k][t] = r[k].s;
+  }
+  __syncthreads();
+  for (int d = 1; d < kThreads; d <<= 1) {
+    Run o[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = t >= d ? join(Run{sf[k][t - d], ss[k][t - d]}, r[k]) : r[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      sf[k][t] = o[k].f;
+      ss[k][t] = o[k].s;
+      r[k] = o[k];
+    }
+    __syncthreads();
+  }
+}
+
 // The count of smaller keys from each position's segment start through it,
-// in one pass: each workgroup takes the next scan block in claim order (so
-// every block it waits for belongs to a workgroup that has started), scans
-// its kItems x kThreads positions, publishes its run, and finds the run
-// carried into it by decoupled look-back: the nearest earlier block that has
-// published its run from the array's start, or that contains a segment start,
-// ends the look-back.  The first workgroup of a level also clears the
-// level's counters (active positions, filed sides) and the next level's
-// ticket counter.
+// in one pass.  Each workgroup takes the next kScanChunk scan blocks in
+// claim order, so every block it waits for belongs to a workgroup that has
+// started.  It scans the kItems x kThreads positions of each, publishes every
+// block's own run at once, finds the run carried into its first block by
+// decoupled look-back (the nearest earlier block that has published its run
+// from the array's start, or that contains a segment start, ends it), and
+// from that the runs from the array's start through each of its blocks.
+// The first workgroup of a level also clears the level's counters (active
+// positions, filed sides) and the next level's ticket counter.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
-  __shared__ int sf[kThreads], ss[kThreads];
-  __shared__ int s_b, s_pf, s_ps;
+  constexpr int K = kScanChunk;
+  __shared__ int sf[K][kThreads], ss[K][kThreads];
+  __shared__ int s_b, s_pf[K], s_ps[K];
   if (threadIdx.x == 0) {
-    const int b = atomicAdd(a.sctr + a.par, 1);
-    s_b = b;
-    if (b == 0) {
+    const int c = atomicAdd(a.sctr + a.par, 1);
+    s_b = c * K;
+    if (c == 0) {
       a.sctr[a.par ^ 1] = 0;
       if (a.active) *a.active = 0;
       if (a.nsmall) *a.nsmall = 0;
     }
   }
   __syncthreads();
-  const int64_t blk = s_b;
+  const int64_t b0 = s_b;
   uint64_t* st = a.sstat[a.par];
-  if (threadIdx.x == 0) a.sstat[a.par ^ 1][blk] = 0;  // the next level's word starts unpublished
-  if (a.act) {
-    if (threadIdx.x == 0) a.act_next[blk] = 0;
-    if (!a.act[blk]) {  // every position final: a run start that counts nothing
-      if (threadIdx.x == 0) __hip_atomic_store(st + blk, run_word(kRunIncl, Run{1, 0}), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-      return;
+  bool live[K];      // the block exists and has a position in a segment
+  uint32_t fbits[K], lbits[K];  // per item: run start, smaller key
+  Run r[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t blk = b0 + k;
+    live[k] = blk < a.nblocks && (!a.act || a.act[blk]);
+    fbits[k] = lbits[k] = 0;
+    r[k] = Run{1, 0};  // a block that is missing or all final: a run start counting nothing
+    if (blk < a.nblocks && threadIdx.x == 0) {
+      a.sstat[a.par ^ 1][blk] = 0;  // the next level's word starts unpublished
+      if (a.act) a.act_next[blk] = 0;
+    }
+    if (!live[k]) continue;
+    r[k] = Run{0, 0};
+    const int64_t base = blk * kSpan + (int64_t)threadIdx.x * kItems;
+    if (base + kItems <= a.n) {
+      int32_t h[kItems];
+      T v[kItems];
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        h[j] = a.hd[base + j];
+        v[j] = a.cur[base + j];
+      }
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const bool start = h[j] < 0 || h[j] == base + j;
+        const bool lt = !start && !(a.cur[h[j]] <= v[j]);
+        r[k] = join(r[k], Run{start ? 1 : 0, lt ? 1 : 0});
+        fbits[k] |= (uint32_t)start << j;
+        lbits[k] |= (uint32_t)lt << j;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const Run p = pos_run(a, base + j);
+        r[k] = join(r[k], p);
+        fbits[k] |= (uint32_t)p.f << j;
+        lbits[k] |= (uint32_t)p.s << j;
+      }
     }
   }
-  const int64_t base = blk * kSpan + (int64_t)threadIdx.x * kItems;
-  uint32_t fbits = 0, lbits = 0;  // per item: run start, smaller key
-  Run r{0, 0};
-  if (base + kItems <= a.n) {
-    int32_t h[kItems];
-    T v[kItems];
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      h[j] = a.hd[base + j];
-      v[j] = a.cur[base + j];
-    }
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const bool start = h[j] < 0 || h[j] == base + j;
-      const bool lt = !start && !(a.cur[h[j]] <= v[j]);
-      r = join(r, Run{start ? 1 : 0, lt ? 1 : 0});
-      fbits |= (uint32_t)start << j;
-      lbits |= (uint32_t)lt << j;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const Run p = pos_run(a, base + j);
-      r = join(r, p);
-      fbits |= (uint32_t)p.f << j;
-      lbits |= (uint32_t)p.s << j;
-    }
-  }
-  const Run inc = block_scan<kThreads>(r, sf, ss);
-  // the run carried into this block
+  block_scan_k<K>(r, sf, ss);
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
-    const Run agg{sf[kThreads - 1], ss[kThreads - 1]};
+    // every block's own run first, so later workgroups can look back
+    // across this chunk while its first block waits
+    if (lane < K && b0 + lane < a.nblocks && b0 + lane > 0) {
+      const Run agg{sf[lane][kThreads - 1], ss[lane][kThreads - 1]};
+      __hip_atomic_store(st + b0 + lane, run_word(kRunOwn, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     Run pre{0, 0};
-    if (blk == 0) {
-      if (lane == 0) __hip_atomic_store(st, run_word(kRunIncl, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      if (lane == 0) __hip_atomic_store(st + blk, run_word(kRunOwn, agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int64_t top = blk - 1;  // lane j watches block top - j
+    if (b0 > 0) {
+      int64_t top = b0 - 1;  // lane j watches block top - j
       int sum = 0;
       uint32_t polls = 0;
       for (;;) {
@@ -239,45 +281,54 @@ __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
         // array's start, or a run with a segment start in it
         const bool stop = j >= 0 && ((w >> 33) == kRunIncl || ((w >> 32) & 1));
         const uint64_t sm = __ballot(stop);
-        const int first = sm ? __builtin_ctzll(sm) : 64;
+        const int first_stop = sm ? __builtin_ctzll(sm) : 64;
         const Run wr = word_run(w);
-        int part = j >= 0 && lane < first ? wr.s : 0;
+        int part = j >= 0 && lane < first_stop ? wr.s : 0;
         for (int d = 32; d > 0; d >>= 1) part += __shfl_xor(part, d);
         sum += part;
         if (sm) {
-          const uint64_t ws = __shfl(w, first);
+          const uint64_t ws = __shfl(w, first_stop);
           const Run rs = word_run(ws);
           pre = Run{rs.f, rs.s + sum};
           break;
         }
         top -= 64;
       }
-      if (lane == 0) {
-        __hip_atomic_store(st + blk, run_word(kRunIncl, join(pre, agg)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
     }
+    // runs from the array's start through each block of the chunk
     if (lane == 0) {
-      s_pf = pre.f;
-      s_ps = pre.s;
+      Run acc = pre;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        s_pf[k] = acc.f;
+        s_ps[k] = acc.s;
+        acc = join(acc, Run{sf[k][kThreads - 1], ss[k][kThreads - 1]});
+        if (b0 + k < a.nblocks)
+          __hip_atomic_store(st + b0 + k, run_word(kRunIncl, acc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
   __syncthreads();
-  Run run = join(Run{s_pf, s_ps}, threadIdx.x > 0 ? Run{sf[threadIdx.x - 1], ss[threadIdx.x - 1]} : Run{0, 0});
-  (void)inc;
-  int32_t out[kItems];
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    run = join(run, Run{(int)((fbits >> j) & 1), (int)((lbits >> j) & 1)});
-    out[j] = run.s;
-  }
-  if (base + kItems <= a.n) {
+  for (int k = 0; k < K; ++k) {
+    if (!live[k]) continue;
+    const int64_t base = (b0 + k) * kSpan + (int64_t)threadIdx.x * kItems;
+    Run run = join(Run{s_pf[k], s_ps[k]}, threadIdx.x > 0 ? Run{sf[k][threadIdx.x - 1], ss[k][threadIdx.x - 1]} : Run{0, 0});
+    int32_t out[kItems];
 #pragma unroll
-    for (int q = 0; q < kItems / 4; ++q)
-      *(int4*)(a.ltp + base + 4 * q) = make_int4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
-  } else {
+    for (int j = 0; j < kItems; ++j) {
+      run = join(run, Run{(int)((fbits[k] >> j) & 1), (int)((lbits[k] >> j) & 1)});
+      out[j] = run.s;
+    }
+    if (base + kItems <= a.n) {
 #pragma unroll
-    for (int j = 0; j < kItems; ++j)
-      if (base + j < a.n) a.ltp[base + j] = out[j];
+      for (int q = 0; q < kItems / 4; ++q)
+        *(int4*)(a.ltp + base + 4 * q) = make_int4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kItems; ++j)
+        if (base + j < a.n) a.ltp[base + j] = out[j];
+    }
   }
 }
 
@@ -597,27 +648,63 @@ __global__ __launch_bounds__(kThreads) void gather_pivots(const int32_t* piv_at,
 
 static int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kThreads - 1) / kThreads, kPairGrid)); }
 
-// Device buffers of one run, freed on scope exit.
-struct Buffers {
-  std::vector<void*> ptrs;
-  ~Buffers() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
+// Device scratch of a call, laid out in two passes over the same sequence
+// of take() calls: the first (no base) measures, the second hands out
+// pieces of an arena of at least that size.
+struct Carve {
+  char* base = nullptr;
+  size_t off = 0;
   template <typename P>
   int take(P** out, size_t count) {
-    void* p = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&p, count * sizeof(P));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
-    ptrs.push_back(p);
-    *out = (P*)p;
+    *out = base ? (P*)(base + off) : nullptr;
+    off += (count * sizeof(P) + 255) & ~(size_t)255;
     return KSORT_OK;
   }
 };
 
+// Scratch kept per (device, stream) between calls and grown on demand (a
+// call's own allocations and frees cost about 3 ms at 7e6 keys, as much as
+// a third of the sort), with a pinned word pair for the read-backs.  The
+// lock is held for a whole call.
+struct Arena {
+  std::mutex mu;
+  void* base = nullptr;
+  size_t bytes = 0;
+  unsigned long long* h = nullptr;
+};
+
+static std::mutex g_arena_mu;
+// never destroyed: calls may run during static destruction of the process
+static auto* g_arenas = new std::map<std::pair<int, hipStream_t>, std::unique_ptr<Arena>>();
+
+static Arena* arena_for(hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_arena_mu);
+  auto& p = (*g_arenas)[std::make_pair(dev, st)];
+  if (!p) p.reset(new Arena);
+  return p.get();
+}
+
+// Makes the arena hold `need` bytes (the caller holds its lock).
+static int arena_reserve(Arena& A, size_t need, hipStream_t st) {
+  if (!A.h) KSORT_HIP(hipHostMalloc((void**)&A.h, 2 * sizeof(unsigned long long), hipHostMallocDefault));
+  if (need <= A.bytes) return KSORT_OK;
+  if (A.base) {
+    KSORT_HIP(hipStreamSynchronize(st));
+    KSORT_HIP(hipFree(A.base));
+    A.base = nullptr;
+    A.bytes = 0;
+  }
+  KSORT_HIP(hipMalloc(&A.base, need));
+  A.bytes = need;
+  return KSORT_OK;
+}
+
 // Buffers of a level; hd[1] and ln[1] (the next level's) only in sort mode.
 template <typename T>
-static int alloc_level(Buffers& B, LevelArgs<T>& a, int64_t n, bool sort_mode, int32_t* hd[2], int32_t* ln[2]) {
+static int alloc_level(Carve& B, LevelArgs<T>& a, int64_t n, bool sort_mode, int32_t* hd[2], int32_t* ln[2]) {
   int rc = 0;
   const int64_t nb = (n + kSpan - 1) / kSpan;
   a.n = n;
@@ -628,7 +715,7 @@ static int alloc_level(Buffers& B, LevelArgs<T>& a, int64_t n, bool sort_mode, i
       (rc = B.take(&a.rkey, (size_t)n)) || (rc = B.take(&a.sstat[0], (size_t)2 * nb)) ||
       (rc = B.take(&a.sctr, 2)) || (rc = B.take(&a.err, 1)))
     return rc;
-  a.sstat[1] = a.sstat[0] + nb;
+  a.sstat[1] = a.sstat[0] ? a.sstat[0] + nb : nullptr;
   a.spin_limit = spin_limit_setting();
   if (sort_mode) {
     if ((rc = B.take(&hd[1], (size_t)n)) || (rc = B.take(&ln[1], (size_t)n)) || (rc = B.take(&a.active, 1))) return rc;
@@ -652,7 +739,7 @@ static int clear_scan_state(const LevelArgs<T>& a, hipStream_t st) {
 template <typename T>
 static int launch_level(const LevelArgs<T>& a, hipStream_t st) {
   const int nb = a.nblocks;
-  hipLaunchKernelGGL(scan_level<T>, dim3(nb), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(scan_level<T>, dim3((nb + kScanChunk - 1) / kScanChunk), dim3(kThreads), 0, st, a);
   hipLaunchKernelGGL(move_kernel<T>, dim3(grid_for(a.n)), dim3(kThreads), 0, st, a);
   hipLaunchKernelGGL(pair_kernel<T>, dim3(grid_for(a.n)), dim3(kThreads), 0, st, a);
   if (a.small) hipLaunchKernelGGL(small_kernel<T>, dim3(kSmallGrid), dim3(kThreads), 0, st, a);
@@ -682,32 +769,37 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
     }
     return KSORT_OK;
   }
-  Buffers B;
+  Arena* A = arena_for(st);
+  if (!A) return fail(KSORT_EHIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(A->mu);
   LevelArgs<T> a{};
   int32_t *H[2], *Ln[2];
-  int rc = alloc_level<T>(B, a, n, true, H, Ln);
-  if (rc) return rc;
   T* scratch = nullptr;
-  if ((rc = B.take(&scratch, (size_t)n))) return rc;
-  unsigned long long* h_active = nullptr;
-  KSORT_HIP(hipHostMalloc((void**)&h_active, 2 * sizeof(unsigned long long), hipHostMallocDefault));
-  struct HostFree {
-    void* p;
-    ~HostFree() { (void)hipHostFree(p); }
-  } hf{h_active};
   uint8_t* act_ring = nullptr;  // three levels of per-block activity flags
-  if ((rc = B.take(&act_ring, (size_t)3 * a.nblocks))) return rc;
-  if ((rc = B.take(&a.small, (size_t)(n / 2 + 1))) || (rc = B.take(&a.nsmall, 1))) return rc;
+  const bool count_per_group = d_ncalls && !d_calls;  // calls counted per workgroup, summed at the end
+  auto layout = [&](Carve& B) {
+    int r = alloc_level<T>(B, a, n, true, H, Ln);
+    if (!r) r = B.take(&scratch, (size_t)n);
+    if (!r) r = B.take(&act_ring, (size_t)3 * a.nblocks);
+    if (!r) r = B.take(&a.small, (size_t)(n / 2 + 1));
+    if (!r) r = B.take(&a.nsmall, 1);
+    if (!r && count_per_group) r = B.take(&a.wcalls, (size_t)(kPairGrid + kSmallGrid));
+    return r;
+  };
+  Carve measure;
+  int rc = layout(measure);
+  if (rc || (rc = arena_reserve(*A, measure.off, st))) return rc;
+  Carve B;
+  B.base = (char*)A->base;
+  if ((rc = layout(B))) return rc;
+  unsigned long long* h_active = A->h;
   KSORT_HIP(hipMemsetAsync(act_ring, 1, (size_t)3 * a.nblocks, st));
   a.sort_mode = 1;
   a.calls = d_calls;
   a.calls_cap = d_calls ? calls_cap : 0;
   a.ncalls = (unsigned long long*)d_ncalls;
-  if (d_ncalls && !d_calls) {
-    // calls counted per workgroup, summed once at the end
-    if ((rc = B.take(&a.wcalls, (size_t)(kPairGrid + kSmallGrid)))) return rc;
+  if (count_per_group)
     KSORT_HIP(hipMemsetAsync(a.wcalls, 0, (size_t)(kPairGrid + kSmallGrid) * sizeof(unsigned long long), st));
-  }
   if ((rc = clear_scan_state<T>(a, st))) return rc;
   hipLaunchKernelGGL(init_whole, dim3(grid_for(n)), dim3(kThreads), 0, st, H[0], Ln[0], n);
   KSORT_HIP(hipGetLastError());
@@ -779,16 +871,28 @@ static int level_exact(const T* d_in, T* d_out, int64_t n, const int64_t* d_left
       clen.push_back(hn[s]);
       cs.push_back(p);
     }
-  Buffers B;
+  Arena* A = arena_for(st);
+  if (!A) return fail(KSORT_EHIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(A->mu);
   LevelArgs<T> a{};
   int32_t *H[2], *Ln[2];
-  int rc = alloc_level<T>(B, a, n, false, H, Ln);
-  if (rc) return rc;
   int64_t *dcl = nullptr, *dclen = nullptr, *dcs = nullptr;
   uint8_t* dok = nullptr;
-  if ((rc = B.take(&dcl, cl.size())) || (rc = B.take(&dclen, cl.size())) || (rc = B.take(&dcs, cl.size())) ||
-      (rc = B.take(&dok, (size_t)nseg)) || (rc = B.take(&a.piv_at, (size_t)n)))
-    return rc;
+  auto layout = [&](Carve& B) {
+    int r = alloc_level<T>(B, a, n, false, H, Ln);
+    if (!r) r = B.take(&dcl, cl.size());
+    if (!r) r = B.take(&dclen, cl.size());
+    if (!r) r = B.take(&dcs, cl.size());
+    if (!r) r = B.take(&dok, (size_t)nseg);
+    if (!r) r = B.take(&a.piv_at, (size_t)n);
+    return r;
+  };
+  Carve measure;
+  int rc = layout(measure);
+  if (rc || (rc = arena_reserve(*A, measure.off, st))) return rc;
+  Carve B;
+  B.base = (char*)A->base;
+  if ((rc = layout(B))) return rc;
   KSORT_HIP(hipMemcpyAsync(dcl, cl.data(), cl.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
   KSORT_HIP(hipMemcpyAsync(dclen, clen.data(), clen.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
   KSORT_HIP(hipMemcpyAsync(dcs, cs.data(), cs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
@@ -804,15 +908,28 @@ static int level_exact(const T* d_in, T* d_out, int64_t n, const int64_t* d_left
   if ((rc = launch_level<T>(a, st))) return rc;
   hipLaunchKernelGGL(gather_pivots, dim3(grid_for(nseg)), dim3(kThreads), 0, st, a.piv_at, d_left, dok, nseg, d_pivot);
   KSORT_HIP(hipGetLastError());
-  int32_t h_err = 0;
-  KSORT_HIP(hipMemcpyAsync(&h_err, a.err, sizeof h_err, hipMemcpyDeviceToHost, st));
+  KSORT_HIP(hipMemcpyAsync(A->h, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   KSORT_HIP(hipStreamSynchronize(st));
-  if (h_err) return fail(KSORT_EINTERNAL, "a look-back wait timed out");
+  if (((const int32_t*)A->h)[0] != 0) return fail(KSORT_EINTERNAL, "a look-back wait timed out");
   if (bad) return fail(KSORT_EINVAL, "a segment is outside [0, n) or has len < 1");
   return KSORT_OK;
 }
 
 }  // namespace exact
+
+void release_exact_arenas() {
+  std::lock_guard<std::mutex> lk(exact::g_arena_mu);
+  for (auto& kv : *exact::g_arenas) {
+    exact::Arena& A = *kv.second;
+    std::lock_guard<std::mutex> al(A.mu);
+    if (A.base) (void)hipFree(A.base);
+    if (A.h) (void)hipHostFree(A.h);
+    A.base = nullptr;
+    A.h = nullptr;
+    A.bytes = 0;
+  }
+}
+
 }  // namespace ksort
 
 using namespace ksort;

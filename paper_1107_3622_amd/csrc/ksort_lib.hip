@@ -68,6 +68,7 @@ static Variant make_variant(int dtype) {
 const std::vector<Variant>& variants() {
   static const std::vector<Variant> vs = {
       make_variant<double, 512, 24, 2048>(KSORT_F64),
+      make_variant<double, 512, 28, 2048>(KSORT_F64),
       make_variant<double, 512, 16, 2048>(KSORT_F64),
       make_variant<double, 1024, 8, 2048>(KSORT_F64),
       make_variant<double, 512, 16, 1024>(KSORT_F64),
@@ -1067,6 +1068,7 @@ int ksort_release_workspaces(void) {
     g_graphs.clear();
   }
   release_workspaces();
+  release_exact_arenas();
   return KSORT_OK;
 }
 
