@@ -14,11 +14,12 @@ Prints ONE JSON line:
   batched               4096 arrays (log-uniform lengths in [32, 65536]) in
                         one segmented call vs 4096 plain calls vs one plain
                         sort of the same key count
-  serve                 the serving workload's shape: a seeded Poisson stream
-                        of requests of 1e3 .. 1e7 keys drawn on the device as
-                        they arrive, through the sort server (p50/p99 latency
-                        and keys/s beside the plain path), then a saturation
-                        run
+  serve                 the serving workload (c4): a seeded Poisson stream
+                        of 20,000 requests of 1e3 .. 1e7 keys (drawn on the
+                        device before the stream), 256 in flight, through the
+                        sort server (p50/p99 latency and keys/s beside the
+                        plain path), then a saturation run; in a child
+                        process with a time limit
   statbound             the paper's run-time model (Section 3) fitted to
                         this sort over Table 1's sizes
   worst_case            sorted, reversed, all-equal and four-valued inputs:
@@ -33,7 +34,10 @@ Prints ONE JSON line:
   cpu_parallel          its task-parallel driver on up to 16 host cores
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-extras]
-                  [--copy-probe BYTES] [--exact-only]
+                  [--copy-probe BYTES] [--exact-only] [--profile-sort WORKLOAD]
+                  [--serve-only REQUESTS INFLIGHT [--serve-oracle K] [--serve-alone K]]
+  (the default run's serve leg is --serve-only 20000 256 --serve-oracle 200
+  --serve-alone 200)
 """
 from __future__ import annotations
 
@@ -71,6 +75,10 @@ def parse():
     p.add_argument("--readings", type=int, default=50, help="sorts per size in the statistical-bound leg")
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only run device copies of this many bytes (counter calibration)")
+    p.add_argument("--serve-only", type=int, nargs=2, default=None, metavar=("REQUESTS", "INFLIGHT"),
+                   help="run only the serving leg, at this many requests and in-flight slots")
+    p.add_argument("--serve-oracle", type=int, default=6, help="requests of the serving leg checked with the oracle")
+    p.add_argument("--serve-alone", type=int, default=4, help="of those, requests also served alone and compared")
     p.add_argument("--exact-only", action="store_true",
                    help="only run the literal-arrangement leg on the workload (profiling)")
     p.add_argument("--profile-sort", default=None, metavar="WORKLOAD",
@@ -270,12 +278,12 @@ def batched_leg(ksort, torch) -> dict:
             "verified": bool(ok)}
 
 
-def _plain_rate(ksort, torch, sizes, kinds) -> float:
-    """Keys/s of the plain single-array path over the stream's requests, one
-    call per request, inputs resident."""
+def _plain_rate(ksort, torch, sizes, kinds, sample: int) -> float:
+    """Keys/s of the plain single-array path over the first `sample`
+    requests of the stream, one call per request, inputs resident."""
     import synth
     total_keys, total_s = 0, 0.0
-    for r in range(len(sizes)):
+    for r in range(min(sample, len(sizes))):
         t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
         fn = ksort.ksort_f64 if t.dtype == torch.float64 else ksort.ksort_f32
         torch.cuda.synchronize()
@@ -291,75 +299,105 @@ SERVE_REQUESTS = 160
 SERVE_INFLIGHT = 128
 
 
-def serve_leg(ksort, torch) -> dict:
-    """The serving workload's shape: a seeded Poisson stream (arrivals seed
-    11) of requests with sizes log-uniform in [1e3, 1e7] (seed 12), 70 % FP64
-    (seed 13), 128 in flight under a 64 GiB budget; lambda = 0.7 x the plain
-    path's keys/s on the same requests / E[n].  Every request's keys are drawn
-    on the device before the server starts and each is submitted at its
-    arrival time.  After the stream every result is compared with torch.sort
-    of its input, and a sample (including the largest requests) with the
-    oracle and its first pivot.  Then a saturation run: the same requests all
-    submitted at t = 0."""
+def serve_leg(ksort, torch, count: int = SERVE_REQUESTS, inflight: int = SERVE_INFLIGHT,
+              oracle_checks: int = 6, alone_checks: int = 4, plain_sample: int = 400) -> dict:
+    """The serving workload: a seeded Poisson stream (arrivals seed 11) of
+    `count` requests with sizes log-uniform in [1e3, 1e7] (seed 12), 70 %
+    FP64 (seed 13), `inflight` in flight under a 64 GiB budget; lambda = 0.7
+    x the plain path's keys/s on the first `plain_sample` requests / E[n].
+    Every request's keys are drawn on the device before the server starts
+    and each is submitted at its arrival time.  After the stream every result
+    is compared with torch.sort of its input; `oracle_checks` requests
+    (evenly spread, the three largest among them) with the oracle and their
+    first pivots, and `alone_checks` of them with their results when served
+    alone.  Then a saturation run: the same requests all submitted at t = 0."""
     import numpy as np
 
     import oracle
     import synth
-    count, lo, hi, p64 = SERVE_REQUESTS, 1_000, 10_000_000, 0.7
+    lo, hi, p64 = 1_000, 10_000_000, 0.7
     sizes, is_f64, _ = synth.serve_requests(count, 12, 13, 11, lo, hi, p64, 1.0)
     kinds = ["uniform_f64" if f else "uniform_f32" for f in is_f64]
     e_n = (hi - lo) / (np.log(hi) - np.log(lo))  # mean of the log-uniform size
-    plain = _plain_rate(ksort, torch, sizes, kinds)
+    plain = _plain_rate(ksort, torch, sizes, kinds, plain_sample)
     lam = 0.7 * plain / e_n
     _, _, arrivals = synth.serve_requests(count, 12, 13, 11, lo, hi, p64, lam)
     keys = int(sizes.sum())
+    deadline_s = 120.0 + 4.0 * arrivals[-1]
 
     def draw():
         ts = [synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda") for r in range(count)]
         torch.cuda.synchronize()
         return ts
 
-    log(f"serve: {count} requests, {keys} keys; plain path {plain / 1e9:.2f} G keys/s; lambda {lam:.0f}/s")
+    def wait_all(srv, tks, t0):
+        codes = []
+        for tk in tks:
+            left = max(1.0, deadline_s - (time.perf_counter() - t0))
+            codes.append(srv.wait(tk, left))
+        return codes
+
+    log(f"serve: {count} requests, {keys} keys; plain path {plain / 1e9:.2f} G keys/s; lambda {lam:.0f}/s; "
+        f"{inflight} in flight")
     tensors = draw()
     tickets = []
-    with ksort.Server(64 << 30, SERVE_INFLIGHT) as srv:
+    with ksort.Server(64 << 30, inflight) as srv:
         t0 = time.perf_counter()
         for r in range(count):
             dt = arrivals[r] - (time.perf_counter() - t0)
             if dt > 0:
                 time.sleep(dt)
             tickets.append(srv.submit(tensors[r]))
-        codes = [srv.wait(tk, 120.0) for tk in tickets]
+        codes = wait_all(srv, tickets, t0)
         wall = time.perf_counter() - t0
         st = srv.stats()
         infos = [srv.result(tk) for tk in tickets]
     ok = all(c == 0 for c in codes)
+    log(f"serve: stream done in {wall:.2f} s, {st['completed']} completed; checking against torch.sort")
+    n_equal = 0
     for r in range(count):
         ref = torch.sort(synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda"))[0]
-        ok = ok and bool(torch.equal(tensors[r], ref))
+        n_equal += int(bool(torch.equal(tensors[r], ref)))
+    ok = ok and n_equal == count
     order = np.argsort(sizes)
-    sample = sorted(set([0, 1, 2] + [int(x) for x in order[-3:]]))
+    spread = np.linspace(0, count - 1, max(1, oracle_checks - 3)).astype(int).tolist()
+    sample = sorted(set(spread + [int(x) for x in order[-3:]]))[:max(oracle_checks, 1)]
+    n_oracle = 0
     for r in sample:
         a = (synth.uniform_f64 if is_f64[r] else synth.uniform_f32)(synth.REQUEST_SEED_BASE + r, int(sizes[r]))
         want, wp = oracle.sorted_copy(a)
         got = tensors[r].cpu().numpy()
-        ok = ok and np.array_equal(got.view(np.uint8), want.view(np.uint8)) and infos[r]["first_pivot"] == wp
+        n_oracle += int(np.array_equal(got.view(np.uint8), want.view(np.uint8)) and infos[r]["first_pivot"] == wp)
+    ok = ok and n_oracle == len(sample)
+    # the first alone_checks requests of the sample, each served alone
+    n_alone = 0
+    with ksort.Server(64 << 30, inflight) as srv:
+        for r in sample[:alone_checks]:
+            t = synth.torch_fill(kinds[r], synth.REQUEST_SEED_BASE + r, int(sizes[r]), "cuda")
+            tk = srv.submit(t)
+            c = srv.wait(tk, 60.0)
+            n_alone += int(c == 0 and bool(torch.equal(t, tensors[r])) and
+                           srv.result(tk)["first_pivot"] == infos[r]["first_pivot"])
+            del t
+    ok = ok and n_alone == min(alone_checks, len(sample))
     del tensors
-    # saturation: the same requests, all submitted at t = 0
+    torch.cuda.empty_cache()
+    log("serve: saturation run")
     pre = draw()
-    with ksort.Server(64 << 30, SERVE_INFLIGHT) as srv:
+    with ksort.Server(64 << 30, inflight) as srv:
         t0 = time.perf_counter()
         tks = [srv.submit(t) for t in pre]
-        sat_codes = [srv.wait(tk, 120.0) for tk in tks]
+        sat_codes = wait_all(srv, tks, t0)
         sat_wall = time.perf_counter() - t0
         sat = srv.stats()
     ok = ok and all(c == 0 for c in sat_codes)
     del pre
     torch.cuda.empty_cache()
-    return {"workload": f"c4 shape: {count} requests, Poisson arrivals (seed 11), sizes log-uniform [1e3, 1e7] "
+    return {"workload": f"c4: {count} requests, Poisson arrivals (seed 11), sizes log-uniform [1e3, 1e7] "
                         f"(seed 12), 70 % FP64 (seed 13), keys of request r from seed 1,000,000 + r drawn on the "
-                        f"device before the stream, {SERVE_INFLIGHT} in flight, 64 GiB budget",
-            "requests": count, "keys": keys, "lambda_per_s": lam, "plain_keys_per_s_on_mix": plain,
+                        f"device before the stream, {inflight} in flight, 64 GiB budget",
+            "requests": count, "inflight": inflight, "keys": keys, "lambda_per_s": lam,
+            "plain_keys_per_s_on_mix": plain, "plain_sample_requests": min(plain_sample, count),
             "wall_s": wall, "keys_per_s": keys / wall,
             "keys_per_busy_s": keys / st["busy_s"] if st["busy_s"] > 0 else None,
             "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
@@ -369,7 +407,34 @@ def serve_leg(ksort, torch) -> dict:
                            "wall_s": sat_wall, "keys_per_s": keys / sat_wall,
                            "p50_latency_s": sat["p50_latency_s"], "p99_latency_s": sat["p99_latency_s"],
                            "ticks": sat["ticks"], "completed": sat["completed"]},
-            "oracle_sample": len(sample), "verified": bool(ok)}
+            "equal_to_torch_sort": n_equal, "oracle_checked": len(sample), "oracle_equal": n_oracle,
+            "alone_checked": min(alone_checks, len(sample)), "alone_equal": n_alone, "verified": bool(ok)}
+
+
+SERVE_C4 = (20_000, 256, 200, 200)  # requests, in flight, oracle checks, alone checks
+
+
+def serve_in_child(torch, timeout_s: float = 900.0) -> dict:
+    """The serving leg at its configuration (20,000 requests, 256 in
+    flight) in a child process with a time limit, so that a server that
+    stops making progress costs this leg, not the whole run."""
+    import subprocess
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    count, inflight, n_or, n_al = SERVE_C4
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serve-only", str(count), str(inflight),
+           "--serve-oracle", str(n_or), "--serve-alone", str(n_al)]
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, timeout=timeout_s, text=True)
+    except subprocess.TimeoutExpired:
+        return {"error": f"the serving leg did not finish within {timeout_s:.0f} s", "verified": False}
+    lines = [x for x in r.stdout.strip().splitlines() if x.startswith("{")]
+    if not lines:
+        return {"error": f"the serving leg exited with status {r.returncode} and no result", "verified": False}
+    res = json.loads(lines[-1])["serve"]
+    if r.returncode != 0:
+        res["verified"] = False
+    return res
 
 
 TABLE1_N = [100_000, 500_000, 1_000_000, 2_500_000, 5_000_000, 6_000_000, 7_000_000, 7_100_000, 7_500_000,
@@ -555,6 +620,12 @@ def main() -> int:
         return copy_probe(args.copy_probe)
     if args.profile_sort:
         return profile_sort(args.profile_sort)
+    if args.serve_only:
+        count, inflight = args.serve_only
+        res = serve_leg(ksort, torch, count, inflight, oracle_checks=args.serve_oracle,
+                        alone_checks=args.serve_alone)
+        print(json.dumps({"serve": res}), flush=True)
+        return 0 if res["verified"] else 3
     if args.exact_only:
         w = synth.WORKLOADS[args.workload]
         res = exact_leg(ksort, torch, synth.torch_fill(w["kind"], w["seed"], w["n"], torch.device("cuda:0")))
@@ -659,8 +730,8 @@ def main() -> int:
     if not args.no_extras:
         log("batched leg")
         out["batched"] = batched_leg(ksort, torch)
-        log("serving leg")
-        out["serve"] = serve_leg(ksort, torch)
+        log("serving leg (child process)")
+        out["serve"] = serve_in_child(torch)
         log("statistical-bound leg")
         out["statbound"] = statbound_leg(ksort, torch, args.readings)
         log("worst-case leg")
