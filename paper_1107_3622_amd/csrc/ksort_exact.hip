@@ -89,10 +89,14 @@ struct LevelArgs {
   const uint8_t* act;
   const uint8_t* act_prev;
   uint8_t* act_next;
-  // sort mode: sides of 2 .. kShort keys filed this level as (left, len);
-  // small_kernel makes all their remaining calls.  Null in level mode.
+  // sort mode: sides of 2 .. kShort keys filed this level as (left, len),
+  // in one list of small_cap entries per workgroup of pair_kernel (npair of
+  // them), with its length in nsmall[workgroup]; small_kernel makes all
+  // their remaining calls.  Null in level mode.
   int2* small;
   int32_t* nsmall;
+  int32_t small_cap;
+  int32_t npair;
 };
 
 // A block whose positions are all final at this level and the one before
@@ -201,7 +205,6 @@ __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
     if (c == 0) {
       a.sctr[a.par ^ 1] = 0;
       if (a.active) *a.active = 0;
-      if (a.nsmall) *a.nsmall = 0;
     }
   }
   __syncthreads();
@@ -395,9 +398,12 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
   constexpr int NW = kThreads / 64;
   __shared__ int32_t fcnt[NW + 1];
+  __shared__ int32_t s_filed;  // sides this workgroup has filed
   unsigned long long ncall = 0;
   bool any_active = false;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_filed = 0;
+  __syncthreads();
   // Every thread of a workgroup runs the same iterations (the bound is on
   // the workgroup's first position), so the barriers below are uniform.
   for (int64_t base = (int64_t)blockIdx.x * kThreads; base < a.n; base += (int64_t)gridDim.x * kThreads) {
@@ -474,8 +480,9 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
       }
     }
     if (a.small) {
-      // the workgroup's filed sides take one range of the list: one
-      // atomic per workgroup and iteration, not per wave
+      // the workgroup's filed sides go to its own list (no atomics: a
+      // shared counter serves only a few tens of millions of additions per
+      // second)
       const uint64_t fm = __ballot(file);
       if (lane == 0) fcnt[w] = (int32_t)__popcll(fm);
       __syncthreads();
@@ -486,16 +493,20 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
           fcnt[j] = tot;
           tot += c;
         }
-        fcnt[NW] = tot ? atomicAdd(a.nsmall, tot) : 0;
+        fcnt[NW] = s_filed;
+        s_filed += tot;
       }
       __syncthreads();
-      if (file) a.small[fcnt[NW] + fcnt[w] + __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
+      if (file)
+        a.small[(int64_t)blockIdx.x * a.small_cap + fcnt[NW] + fcnt[w] +
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
       __syncthreads();  // fcnt is rewritten in the next iteration
     }
   }
   // The next level runs while any position is in a segment of two or more
   // keys: a flag, set with plain stores.  Calls are counted per workgroup.
   if (a.sort_mode && __syncthreads_or(any_active) && threadIdx.x == 0) *a.active = 1ull;
+  if (a.small && threadIdx.x == 0) a.nsmall[blockIdx.x] = s_filed;
   if (a.wcalls) {
     __shared__ unsigned long long csum;
     if (threadIdx.x == 0) csum = 0;
@@ -523,10 +534,10 @@ __global__ __launch_bounds__(kThreads) void small_kernel(LevelArgs<T> a) {
   __shared__ int32_t qs[NW][kShort + 1], rs[NW][kShort + 1];
   __shared__ T vs[NW][kShort];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int32_t cnt = *a.nsmall;
   unsigned long long ncall = 0;
-  for (int32_t e = (int32_t)blockIdx.x * NW + w; e < cnt; e += (int32_t)gridDim.x * NW) {
-    const int2 sg = a.small[e];
+  for (int32_t l = (int32_t)blockIdx.x; l < a.npair; l += (int32_t)gridDim.x)
+  for (int32_t e = w, cnt = a.nsmall[l]; e < cnt; e += NW) {
+    const int2 sg = a.small[(int64_t)l * a.small_cap + e];
     const int64_t gl = sg.x;
     const int L = sg.y;
     T v = lane < L ? a.nxt[gl + lane] : T(0);
@@ -777,12 +788,16 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
   T* scratch = nullptr;
   uint8_t* act_ring = nullptr;  // three levels of per-block activity flags
   const bool count_per_group = d_ncalls && !d_calls;  // calls counted per workgroup, summed at the end
+  // per pair_kernel workgroup: its iterations of kThreads positions, each
+  // filing at most kThreads / 2 sides (disjoint, two keys or more)
+  a.npair = grid_for(n);
+  a.small_cap = (int32_t)(((n + (int64_t)a.npair * kThreads - 1) / ((int64_t)a.npair * kThreads)) * (kThreads / 2) + 1);
   auto layout = [&](Carve& B) {
     int r = alloc_level<T>(B, a, n, true, H, Ln);
     if (!r) r = B.take(&scratch, (size_t)n);
     if (!r) r = B.take(&act_ring, (size_t)3 * a.nblocks);
-    if (!r) r = B.take(&a.small, (size_t)(n / 2 + 1));
-    if (!r) r = B.take(&a.nsmall, 1);
+    if (!r) r = B.take(&a.small, (size_t)a.npair * a.small_cap);
+    if (!r) r = B.take(&a.nsmall, (size_t)a.npair);
     if (!r && count_per_group) r = B.take(&a.wcalls, (size_t)(kPairGrid + kSmallGrid));
     return r;
   };
