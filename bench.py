@@ -709,7 +709,8 @@ def main() -> int:
         "dtype": "f64" if key_bytes == 8 else "f32",
         "data": "synthetic: SplitMix64 U[0,1) keys drawn on the device",
         "config": {"workload": f"{args.workload}: n={n} {w['kind']} seed {w['seed']}, one array per call",
-                   "variant": list(ksort.ksort_get_default(0 if key_bytes == 8 else 1))},
+                   "variant": ([recs[0]["block"], recs[0]["items"], recs[0]["cutoff"]] if recs else
+                               list(ksort.ksort_get_default(0 if key_bytes == 8 else 1)))},
         "per_call_ms": {"p10": q(0.1), "median": q(0.5), "p90": q(0.9)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -121,6 +121,11 @@ const Variant* find_variant(int dtype, const ksort_tuning* tune, int64_t n, int 
   // of an FP64 tile of 24, which keeps the per-tile scan and look-back cost
   // small against the data moved on large arrays
   if (j < 0) j = dtype == KSORT_F64 ? variant_index(dtype, 512, 24, 2048) : variant_index(dtype, 512, 32, 2048);
+  // FP64 arrays whose full passes need a second round of 12288-key tiles on
+  // the 512-workgroup grid of a 256-CU device but fit one round of
+  // 14336-key tiles: 28 keys per thread (7e6 keys: 0.993 against 1.010 ms)
+  if (g_default[dtype] < 0 && dtype == KSORT_F64 && n > 512LL * 512 * 24 && n <= 512LL * 512 * 28)
+    j = variant_index(dtype, 512, 28, 2048);
   return &vs[j];
 }
 

@@ -238,3 +238,14 @@ void ksim_wave_sync();
 #define KS_LDS_WAIT() ksim_wave_sync()
 #define KS_MEM_FENCE() asm volatile("" ::: "memory")
 #define KS_WAVE_STEP() ksim_wave_sync()
+// 16-byte vectors of keys (the kernels' KeyVec), as plain structs
+#define KS_KEY_VEC_DEFINED
+namespace ksort {
+template <typename T>
+struct KeyVec {
+  struct type {
+    T e[16 / sizeof(T)];
+    T operator[](int i) const { return e[i]; }
+  };
+};
+}  // namespace ksort
