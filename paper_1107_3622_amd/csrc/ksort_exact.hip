@@ -90,14 +90,23 @@ struct LevelArgs {
   const uint8_t* act_prev;
   uint8_t* act_next;
   // sort mode: sides of 2 .. kShort keys filed this level as (left, len),
-  // in one list of small_cap entries per workgroup of pair_kernel (npair of
-  // them), with its length in nsmall[workgroup]; small_kernel makes all
-  // their remaining calls.  Null in level mode.
+  // in ngroups lists of small_cap entries each, one per group of
+  // consecutive pair_kernel workgroups (npair of them), with the lengths in
+  // nsmall[group]; small_kernel makes all their remaining calls.  Null in
+  // level mode.
   int2* small;
   int32_t* nsmall;
-  int32_t small_cap;
+  int64_t small_cap;
   int32_t npair;
+  int32_t ngroups;
 };
+
+// Lists of short sides: one shared counter for all pair_kernel workgroups
+// serializes their additions (a device-scope atomic on one address serves
+// a few tens of millions per second); one list per workgroup leaves
+// small_kernel unbalanced.  kSmallGroups lists, each shared by a group of
+// consecutive workgroups, keep both small.
+constexpr int kSmallGroups = 64;
 
 // A block whose positions are all final at this level and the one before
 // holds the same keys and segment state in both buffers: nothing to do.
@@ -205,6 +214,8 @@ __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
     if (c == 0) {
       a.sctr[a.par ^ 1] = 0;
       if (a.active) *a.active = 0;
+      if (a.nsmall)
+        for (int g = 0; g < a.ngroups; ++g) a.nsmall[g] = 0;
     }
   }
   __syncthreads();
@@ -398,12 +409,11 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
   constexpr int NW = kThreads / 64;
   __shared__ int32_t fcnt[NW + 1];
-  __shared__ int32_t s_filed;  // sides this workgroup has filed
   unsigned long long ncall = 0;
   bool any_active = false;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_filed = 0;
-  __syncthreads();
+  // this workgroup's list of short sides (sort mode)
+  const int32_t grp = a.small ? (int32_t)((int64_t)blockIdx.x * a.ngroups / a.npair) : 0;
   // Every thread of a workgroup runs the same iterations (the bound is on
   // the workgroup's first position), so the barriers below are uniform.
   for (int64_t base = (int64_t)blockIdx.x * kThreads; base < a.n; base += (int64_t)gridDim.x * kThreads) {
@@ -480,9 +490,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
       }
     }
     if (a.small) {
-      // the workgroup's filed sides go to its own list (no atomics: a
-      // shared counter serves only a few tens of millions of additions per
-      // second)
+      // the workgroup's filed sides take one range of its group's list
       const uint64_t fm = __ballot(file);
       if (lane == 0) fcnt[w] = (int32_t)__popcll(fm);
       __syncthreads();
@@ -493,12 +501,11 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
           fcnt[j] = tot;
           tot += c;
         }
-        fcnt[NW] = s_filed;
-        s_filed += tot;
+        fcnt[NW] = tot ? atomicAdd(a.nsmall + grp, tot) : 0;
       }
       __syncthreads();
       if (file)
-        a.small[(int64_t)blockIdx.x * a.small_cap + fcnt[NW] + fcnt[w] +
+        a.small[grp * a.small_cap + fcnt[NW] + fcnt[w] +
                 __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
       __syncthreads();  // fcnt is rewritten in the next iteration
     }
@@ -506,7 +513,6 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
   // The next level runs while any position is in a segment of two or more
   // keys: a flag, set with plain stores.  Calls are counted per workgroup.
   if (a.sort_mode && __syncthreads_or(any_active) && threadIdx.x == 0) *a.active = 1ull;
-  if (a.small && threadIdx.x == 0) a.nsmall[blockIdx.x] = s_filed;
   if (a.wcalls) {
     __shared__ unsigned long long csum;
     if (threadIdx.x == 0) csum = 0;
@@ -534,10 +540,27 @@ __global__ __launch_bounds__(kThreads) void small_kernel(LevelArgs<T> a) {
   __shared__ int32_t qs[NW][kShort + 1], rs[NW][kShort + 1];
   __shared__ T vs[NW][kShort];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ int32_t s_end[kSmallGroups];  // inclusive prefix of the list lengths
+  __shared__ int32_t s_total;
   unsigned long long ncall = 0;
-  for (int32_t l = (int32_t)blockIdx.x; l < a.npair; l += (int32_t)gridDim.x)
-  for (int32_t e = w, cnt = a.nsmall[l]; e < cnt; e += NW) {
-    const int2 sg = a.small[(int64_t)l * a.small_cap + e];
+  if (w == 0) {
+    const int32_t c = lane < a.ngroups ? a.nsmall[lane] : 0;
+    int32_t inc = c;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t o = __shfl_up(inc, d);
+      if (lane >= d) inc += o;
+    }
+    s_end[lane] = inc;
+    if (lane == 63) s_total = inc;
+  }
+  __syncthreads();
+  const int32_t total = s_total;
+  for (int32_t e = (int32_t)blockIdx.x * NW + w; e < total; e += (int32_t)gridDim.x * NW) {
+    // the list holding entry e: the first whose prefix exceeds e
+    const uint64_t past = __ballot(s_end[lane] > e);
+    const int l = __builtin_ctzll(past);
+    const int32_t off = e - (l > 0 ? s_end[l - 1] : 0);
+    const int2 sg = a.small[l * a.small_cap + off];
     const int64_t gl = sg.x;
     const int L = sg.y;
     T v = lane < L ? a.nxt[gl + lane] : T(0);
@@ -791,13 +814,20 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
   // per pair_kernel workgroup: its iterations of kThreads positions, each
   // filing at most kThreads / 2 sides (disjoint, two keys or more)
   a.npair = grid_for(n);
-  a.small_cap = (int32_t)(((n + (int64_t)a.npair * kThreads - 1) / ((int64_t)a.npair * kThreads)) * (kThreads / 2) + 1);
+  a.ngroups = std::min(kSmallGroups, a.npair);
+  {
+    // a workgroup's iterations of kThreads positions each file at most
+    // kThreads / 2 sides (disjoint, two keys or more); a group holds at most
+    // ceil(npair / ngroups) workgroups
+    const int64_t iters = (n + (int64_t)a.npair * kThreads - 1) / ((int64_t)a.npair * kThreads);
+    a.small_cap = ((int64_t)a.npair + a.ngroups - 1) / a.ngroups * iters * (kThreads / 2) + 1;
+  }
   auto layout = [&](Carve& B) {
     int r = alloc_level<T>(B, a, n, true, H, Ln);
     if (!r) r = B.take(&scratch, (size_t)n);
     if (!r) r = B.take(&act_ring, (size_t)3 * a.nblocks);
-    if (!r) r = B.take(&a.small, (size_t)a.npair * a.small_cap);
-    if (!r) r = B.take(&a.nsmall, (size_t)a.npair);
+    if (!r) r = B.take(&a.small, (size_t)a.ngroups * a.small_cap);
+    if (!r) r = B.take(&a.nsmall, (size_t)a.ngroups);
     if (!r && count_per_group) r = B.take(&a.wcalls, (size_t)(kPairGrid + kSmallGrid));
     return r;
   };

@@ -151,6 +151,11 @@ template <typename T>
 inline T __shfl_xor(T v, int mask, int width = 64) {
   return __shfl(v, (int)ksim_lane() ^ mask, width);
 }
+template <typename T>
+inline T __shfl_up(T v, unsigned d, int width = 64) {
+  const int l = (int)ksim_lane(), src = l - (int)d;
+  return __shfl(v, src >= l / width * width ? src : l, width);
+}
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 #define __builtin_amdgcn_readfirstlane(v) ((int)ksim_readfirstlane((uint64_t)(uint32_t)(v)))
 #define __builtin_amdgcn_readlane(v, j) ((int)ksim_readlane((uint64_t)(uint32_t)(v), (j)))
