@@ -92,9 +92,10 @@ def kernel_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def stored_traffic():
+def stored_traffic(variant=None):
     """HBM bytes per stage-kernel launch from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
+    or None when the kernel source or the variant that ran changed since the
+    counters were taken."""
     try:
         text = open(PMC_SUMMARY).read()
     except OSError:
@@ -105,6 +106,9 @@ def stored_traffic():
         return None, "counter summary incomplete"
     if m_sha.group(1) != kernel_sha():
         return None, "kernel changed since the counters were taken"
+    m_v = re.search(r"variant:\s*(\d+)\s+(\d+)\s+(\d+)", text)
+    if variant is not None and (not m_v or [int(x) for x in m_v.groups()] != list(variant)):
+        return None, "counters were taken with another kernel variant"
     return float(m_b.group(1)), os.path.relpath(PMC_SUMMARY, ROOT)
 
 
@@ -183,9 +187,11 @@ def profile_sort(workload: str) -> int:
     sort_fn = ksort.ksort_f64 if src.dtype == torch.float64 else ksort.ksort_f32
     kb = src.element_size()
     t = src.clone()
+    log(f"profile-sort {workload}: input drawn")
     sort_fn(t)  # warm-up: workspace
     t.copy_(src)
     torch.cuda.synchronize()
+    log("profile-sort: warm-up sort done")
     ksort.ksort_profile_read()
     ksort.ksort_profile_enable(True)
     sort_fn(t)
@@ -193,13 +199,17 @@ def profile_sort(workload: str) -> int:
     recs = ksort.ksort_profile_read()
     t.copy_(src)
     torch.cuda.synchronize()
+    log("profile-sort: counted sort done")
     sort_fn(t)
     torch.cuda.synchronize()
+    log("profile-sort: plain sort done")
     ok = bool(torch.equal(t, torch.sort(src)[0]))
+    log("profile-sort: checked against torch.sort")
     dst = torch.empty_like(src)
     for _ in range(3):
         ksort.ksort_stream_copy(dst, src)
     torch.cuda.synchronize()
+    log("profile-sort: copies done")
     print(json.dumps({"workload": workload, "n": w["n"], "key_bytes": kb, "verified": ok,
                       "passes": [{"stage": r["stage"], "live_keys": r["live_keys"], "finish_keys": r["finish_keys"],
                                   "alg_bytes": 2 * kb * (r["live_keys"] + r["finish_keys"]), "event_ms": r["ms"]}
@@ -680,7 +690,8 @@ def main() -> int:
     big = [r for r in recs if 2 * key_bytes * r["live_keys"] >= 0.5 * 2 * key_bytes * n]
     big_gbs = (sum(2 * key_bytes * (r["live_keys"] + r["finish_keys"]) for r in big) /
                (sum(r["ms"] for r in big) * 1e-3) / 1e9) if big else None
-    traffic, traffic_src = stored_traffic()
+    ran = [recs[0]["block"], recs[0]["items"], recs[0]["cutoff"]] if recs else None
+    traffic, traffic_src = stored_traffic(ran)
 
     # the read + write rate of the library's streaming copy of the same
     # array (the practical ceiling of one pass at this size)

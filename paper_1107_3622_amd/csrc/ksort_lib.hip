@@ -350,6 +350,13 @@ void release_workspaces() {
 // microseconds; 2^22 polls take seconds.  KSORT_SPIN_LIMIT (a decimal count)
 // overrides it, read whenever a pass is enqueued (a captured graph keeps the
 // value it was captured with); tests use a tiny limit to force the error.
+// Whether the library's own passes give workgroup b ticket b without the
+// counter (KSORT_FIXED_FIRST=0 takes every ticket from the counter).
+static int fixed_first_setting() {
+  const char* s = getenv("KSORT_FIXED_FIRST");
+  return s && s[0] == '0' && s[1] == '\0' ? 0 : 1;
+}
+
 uint32_t spin_limit_setting() {
   constexpr uint32_t kDefault = 1u << 22;
   const char* s = getenv("KSORT_SPIN_LIMIT");
@@ -390,7 +397,7 @@ StageArgs stage_args(Workspace& ws, const Variant& v, int stage, int64_t* pivot_
   a.emit_children = emit_children;
   a.pivot_relative = pivot_relative;
   a.spin_limit = spin_limit_setting();
-  a.fixed_first = 1;
+  a.fixed_first = fixed_first_setting();
   return a;
 }
 
