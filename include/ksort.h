@@ -225,11 +225,13 @@ KSORT_API int ksort_segmented(int dtype, void *d_packed, int64_t n_total,
  *   NULL, per key type (host struct).  Unless a default was set or the size
  *   was tuned, sorts of fewer than 3e6 keys use (512, 16, 1024) instead.
  *   Servers and one-level passes always use the default.
- * ksort_autotune: times every variant on a seeded input of n keys on the
- *   current device and stores the fastest as the variant for single arrays
- *   of about that size (the same power-of-two bucket, or the nearest tuned
- *   bucket at most two powers of two away); `out` (host, nullable) receives
- *   it.  Uses a temporary device buffer of 2n keys.
+ * ksort_autotune: times every variant (best of five runs) on a seeded input
+ *   of n keys on the current device and stores the fastest as the variant
+ *   for single arrays of about that size (the same power-of-two bucket, or
+ *   the nearest tuned bucket at most two powers of two away); the untuned
+ *   default is kept unless another variant is at least 1 % faster.  `out`
+ *   (host, nullable) receives the choice.  Uses a temporary device buffer
+ *   of 2n keys.
  * ksort_autotune_batch: the same for packed batches (ksort_segmented), timed
  *   on copies of the caller's batch (d_packed is left as it is; arguments as
  *   ksort_segmented), keyed by the batch's total key count.  Uses a

@@ -1216,13 +1216,25 @@ __global__ __launch_bounds__(BLOCK) void stage_kernel(StageArgs a) {
     // the upper half of the next stage's finish list
     const int par = a.stage & 1;
     const int32_t nrun = cn.nwork - cn.ntiles;
+    int64_t carried = 0;  // keys of the tasks this thread carried
     for (int32_t j = blockIdx.x * BLOCK + threadIdx.x; j < ndef; j += gridDim.x * BLOCK) {
       Seg d;
       load_seg(&d, (const KS_GLOBAL Seg*)a.fin[par] + fin_slot(a, cn, nrun + j));
       store_seg((KS_GLOBAL Seg*)a.fin[par ^ 1] + a.fin_half + j, d);
-      if (a.stage_keys && a.stage + 1 < a.cap_stats) {
-        atomicAdd((unsigned long long*)&a.stage_keys[2 * (a.stage + 1) + 1], (unsigned long long)d.len);
-        atomicAdd((unsigned long long*)&a.stage_keys[2 * a.stage + 1], (unsigned long long)(-d.len));
+      carried += d.len;
+    }
+    if (a.stage_keys && a.stage + 1 < a.cap_stats) {
+      // profiling: the carried keys move from this stage's count to the
+      // next one's, with one pair of global atomics per workgroup (two per
+      // task cost as much as a pass when a quarter of a million wait)
+      __shared__ unsigned long long s_carried;
+      if (threadIdx.x == 0) s_carried = 0;
+      __syncthreads();
+      if (carried) atomicAdd(&s_carried, (unsigned long long)carried);
+      __syncthreads();
+      if (threadIdx.x == 0 && s_carried) {
+        atomicAdd((unsigned long long*)&a.stage_keys[2 * (a.stage + 1) + 1], s_carried);
+        atomicAdd((unsigned long long*)&a.stage_keys[2 * a.stage + 1], (unsigned long long)(-(int64_t)s_carried));
       }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
