@@ -106,7 +106,7 @@ struct LevelArgs {
 // a few tens of millions per second); one list per workgroup leaves
 // small_kernel unbalanced.  kSmallGroups lists, each shared by a group of
 // consecutive workgroups, keep both small.
-constexpr int kSmallGroups = 64;
+constexpr int kSmallGroups = 256;
 
 // A block whose positions are all final at this level and the one before
 // holds the same keys and segment state in both buffers: nothing to do.
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
       a.sctr[a.par ^ 1] = 0;
       if (a.active) *a.active = 0;
       if (a.nsmall)
-        for (int g = 0; g < a.ngroups; ++g) a.nsmall[g] = 0;
+        for (int g = 0; g < a.ngroups; ++g) a.nsmall[g] = 0;  // (one thread: at most kSmallGroups stores)
     }
   }
   __syncthreads();
@@ -407,15 +407,14 @@ __global__ __launch_bounds__(kThreads) void move_kernel(LevelArgs<T> a) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
-  constexpr int NW = kThreads / 64;
-  __shared__ int32_t fcnt[NW + 1];
   unsigned long long ncall = 0;
   bool any_active = false;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   // this workgroup's list of short sides (sort mode)
   const int32_t grp = a.small ? (int32_t)((int64_t)blockIdx.x * a.ngroups / a.npair) : 0;
   // Every thread of a workgroup runs the same iterations (the bound is on
-  // the workgroup's first position), so the barriers below are uniform.
+  // the workgroup's first position) and the waves file their short sides on
+  // their own, so nothing in the loop waits for the other waves.
   for (int64_t base = (int64_t)blockIdx.x * kThreads; base < a.n; base += (int64_t)gridDim.x * kThreads) {
     if (block_idle(a, base / kSpan)) continue;  // the same span block for the whole workgroup
     const int64_t x = base + threadIdx.x;
@@ -490,24 +489,17 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
       }
     }
     if (a.small) {
-      // the workgroup's filed sides take one range of its group's list
+      // the wave's filed sides take one range of its group's list (one
+      // atomic per wave with sides to file; no workgroup barrier)
       const uint64_t fm = __ballot(file);
-      if (lane == 0) fcnt[w] = (int32_t)__popcll(fm);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int32_t tot = 0;
-        for (int j = 0; j < NW; ++j) {
-          const int32_t c = fcnt[j];
-          fcnt[j] = tot;
-          tot += c;
-        }
-        fcnt[NW] = tot ? atomicAdd(a.nsmall + grp, tot) : 0;
+      if (fm) {
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(a.nsmall + grp, (int32_t)__popcll(fm));
+        base = __shfl(base, 0);
+        if (file)
+          a.small[grp * a.small_cap + base +
+                  __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
       }
-      __syncthreads();
-      if (file)
-        a.small[grp * a.small_cap + fcnt[NW] + fcnt[w] +
-                __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
-      __syncthreads();  // fcnt is rewritten in the next iteration
     }
   }
   // The next level runs while any position is in a segment of two or more
@@ -543,22 +535,35 @@ __global__ __launch_bounds__(kThreads) void small_kernel(LevelArgs<T> a) {
   __shared__ int32_t s_end[kSmallGroups];  // inclusive prefix of the list lengths
   __shared__ int32_t s_total;
   unsigned long long ncall = 0;
+  constexpr int GL = kSmallGroups / 64;  // lists per lane in the prefix
   if (w == 0) {
-    const int32_t c = lane < a.ngroups ? a.nsmall[lane] : 0;
-    int32_t inc = c;
+    int32_t c[GL], sum = 0;
+#pragma unroll
+    for (int q = 0; q < GL; ++q) {
+      c[q] = GL * lane + q < a.ngroups ? a.nsmall[GL * lane + q] : 0;
+      sum += c[q];
+    }
+    int32_t inc = sum;
     for (int d = 1; d < 64; d <<= 1) {
       const int32_t o = __shfl_up(inc, d);
       if (lane >= d) inc += o;
     }
-    s_end[lane] = inc;
+    int32_t run = inc - sum;
+#pragma unroll
+    for (int q = 0; q < GL; ++q) {
+      run += c[q];
+      s_end[GL * lane + q] = run;
+    }
     if (lane == 63) s_total = inc;
   }
   __syncthreads();
   const int32_t total = s_total;
   for (int32_t e = (int32_t)blockIdx.x * NW + w; e < total; e += (int32_t)gridDim.x * NW) {
-    // the list holding entry e: the first whose prefix exceeds e
-    const uint64_t past = __ballot(s_end[lane] > e);
-    const int l = __builtin_ctzll(past);
+    // the list holding entry e: the first whose prefix exceeds e (first the
+    // lane whose last list ends past e, then among that lane's lists)
+    const uint64_t past = __ballot(s_end[GL * lane + GL - 1] > e);
+    int l = GL * __builtin_ctzll(past);
+    while (s_end[l] <= e) ++l;
     const int32_t off = e - (l > 0 ? s_end[l - 1] : 0);
     const int2 sg = a.small[l * a.small_cap + off];
     const int64_t gl = sg.x;
