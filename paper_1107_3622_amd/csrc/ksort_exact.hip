@@ -132,25 +132,6 @@ __device__ __forceinline__ Run pos_run(const LevelArgs<T>& a, int64_t x) {
   return Run{0, !(a.cur[h] <= a.cur[x]) ? 1 : 0};
 }
 
-// Inclusive scan of Run pairs across the workgroup (Hillis-Steele in LDS).
-template <int N>
-__device__ Run block_scan(Run r, int* sf, int* ss) {
-  const int t = threadIdx.x;
-  sf[t] = r.f;
-  ss[t] = r.s;
-  __syncthreads();
-  for (int d = 1; d < N; d <<= 1) {
-    Run o = r;
-    if (t >= d) o = join(Run{sf[t - d], ss[t - d]}, r);
-    __syncthreads();
-    sf[t] = o.f;
-    ss[t] = o.s;
-    r = o;
-    __syncthreads();
-  }
-  return r;
-}
-
 // Look-back word of a scan block: the smaller-key count in bits 0..31, the
 // run flag (a segment starts in the block) in bit 32, and in bits 33..34
 // what the word holds: 1 the block's own run, 2 the run from the array's
@@ -168,29 +149,35 @@ __device__ __forceinline__ Run word_run(uint64_t w) { return Run{(int)((w >> 32)
 constexpr int kScanChunk = 4;
 
 // Inclusive scan of K Run pairs per thread across the workgroup, each of
-// the K sequences on its own (Hillis-Steele in LDS, all K in every step).
+// the K sequences on its own: within each wave by shuffles, then each wave
+// joins the totals of the waves before it (one barrier).  The results are
+// also left in sf/ss (by sequence and thread) for the caller.
 template <int K>
 __device__ void block_scan_k(Run (&r)[K], int (*sf)[kThreads], int (*ss)[kThreads]) {
-  const int t = threadIdx.x;
+  constexpr int NW = kThreads / 64;
+  __shared__ int wf[K][NW], wsum[K][NW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
+    for (int d = 1; d < 64; d <<= 1) {
+      const int pf = __shfl_up(r[k].f, d), ps = __shfl_up(r[k].s, d);
+      if (lane >= d) r[k] = join(Run{pf, ps}, r[k]);
+    }
+    if (lane == 63) {
+      wf[k][w] = r[k].f;
+      wsum[k][w] = r[k].s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    Run pre{0, 0};  // the identity of join
+    for (int j = 0; j < w; ++j) pre = join(pre, Run{wf[k][j], wsum[k][j]});
+    r[k] = join(pre, r[k]);
     sf[k][t] = r[k].f;
     ss[k][t] = r[k].s;
   }
   __syncthreads();
-  for (int d = 1; d < kThreads; d <<= 1) {
-    Run o[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) o[k] = t >= d ? join(Run{sf[k][t - d], ss[k][t - d]}, r[k]) : r[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      sf[k][t] = o[k].f;
-      ss[k][t] = o[k].s;
-      r[k] = o[k];
-    }
-    __syncthreads();
-  }
 }
 
 // The count of smaller keys from each position's segment start through it,
