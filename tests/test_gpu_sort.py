@@ -213,3 +213,42 @@ def test_nan_inputs_stay_a_permutation(ks, n, dt):
         note(f"NaN fraction {frac} n={n} {np.dtype(dt).name}")
         got, _ = gpu_sort(ks, a)
         assert np.array_equal(bits_multiset(got), bits_multiset(a)), f"n={n} frac={frac}: keys lost or duplicated"
+
+
+def test_counter_tickets_sort_the_same(ks, monkeypatch):
+    # KSORT_FIXED_FIRST=0: every work ticket of the library's own passes
+    # comes from the counter (no reliance on the whole grid being resident);
+    # the results are those of the default, for both key types and across
+    # the variants' size ranges, and the plain batched call too.
+    torch = torch_dev()
+    monkeypatch.setenv("KSORT_FIXED_FIRST", "0")
+    for kind, n in (("uniform_f64", 7_000_000), ("uniform_f64", 1_000_000), ("uniform_f32", 3_000_001)):
+        note(f"counter tickets {kind} n={n}")
+        src = synth.torch_fill(kind, 30 + n % 7, n, "cuda")
+        t = src.clone()
+        fp = ks.sort_(t)
+        assert torch.equal(t, torch.sort(src)[0])
+        assert fp == int((src[1:] < src[0]).sum().item())
+    monkeypatch.delenv("KSORT_FIXED_FIRST")
+
+
+def test_stream_copy(ks):
+    # The streaming copy used as the bandwidth ceiling: every byte, for
+    # sizes with and without a tail of less than 16 bytes, and the errors.
+    torch = torch_dev()
+    for nbytes in (16, 48, 17 * 16, (1 << 20) + 16 * 3, (64 << 20) + 16 * 5):
+        note(f"stream copy {nbytes} bytes")
+        src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros_like(src)
+        ks.ksort_stream_copy(dst, src)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+    for nbytes in (1, 15, 33, 1000003):
+        src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros_like(src)
+        ks.ksort_stream_copy(dst, src)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src), nbytes
+    big = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ks.KsortError):
+        ks.ksort_stream_copy(big[1:17], big[32:48])  # not 16-byte aligned
