@@ -247,7 +247,14 @@ KSORT_API int ksort_segmented(int dtype, void *d_packed, int64_t n_total,
  * ksort_tune_count: number of tuning entries known (all architectures).
  * ksort_profile_enable(1) makes every level pass record HIP events on its
  *   stream; ksort_profile_read copies up to `cap` records (host array) and
- *   clears them; ksort_profile_count returns how many are held. */
+ *   clears them; ksort_profile_count returns how many are held.
+ * Environment: KSORT_TRACE=<path> (read at first use) makes every sorting
+ *   call record the same per-pass events and append one JSON line per level
+ *   pass to <path> (call, dtype, stage, live_keys, finish_keys, ms, block,
+ *   items, cutoff, grid); KSORT_ROCTX=1 puts a roctx range around every
+ *   batch of level passes (shown by profilers with host-side markers, for
+ *   example rocprofv3 --marker-trace), loading the roctx library at first
+ *   use if it is installed. */
 typedef struct ksort_level_record {
     int64_t call;         /* sequence number of the sorting call */
     int32_t dtype;

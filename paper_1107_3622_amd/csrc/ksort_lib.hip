@@ -7,6 +7,7 @@
 // segments of stage s+1.  The device keeps all lists and counters, so the host
 // only launches stages in batches and reads one flag word after each batch to
 // learn whether work is left.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -512,11 +513,69 @@ static std::mutex g_prof_mu;
 static std::vector<ksort_level_record> g_prof;
 static std::atomic<int64_t> g_call{0};
 
+// KSORT_TRACE=<path>: every sorting call runs with per-pass events and
+// appends one JSON line per level pass to <path> (read once, at first use).
+static const std::string& trace_path() {
+  static const std::string p = [] {
+    const char* e = getenv("KSORT_TRACE");
+    return std::string(e ? e : "");
+  }();
+  return p;
+}
+
 bool profiling_on() { return g_profile.load() != 0; }
+static bool tracing_on() { return !trace_path().empty(); }
 void profile_push(const ksort_level_record& r) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof.push_back(r);
+  if (profiling_on()) g_prof.push_back(r);
+  if (tracing_on()) {
+    static FILE* f = fopen(trace_path().c_str(), "a");
+    if (f) {
+      fprintf(f,
+              "{\"call\": %lld, \"dtype\": \"%s\", \"stage\": %d, \"live_keys\": %lld, \"finish_keys\": %lld, "
+              "\"ms\": %.6f, \"block\": %d, \"items\": %d, \"cutoff\": %d, \"grid\": %d}\n",
+              (long long)r.call, r.dtype == KSORT_F64 ? "f64" : "f32", r.stage, (long long)r.live_keys,
+              (long long)r.finish_keys, r.ms, r.block, r.items, r.cutoff, r.grid);
+      fflush(f);
+    }
+  }
 }
+
+// KSORT_ROCTX=1: a roctx range around every batch of level passes, for
+// profilers that show host-side markers (rocprofv3 --marker-trace).  The
+// roctx library is loaded at first use, if it is there.
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+static const Roctx& roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    const char* e = getenv("KSORT_ROCTX");
+    if (!e || strcmp(e, "1") != 0) return x;
+    void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return x;
+    x.push = (int (*)(const char*))dlsym(h, "roctxRangePushA");
+    x.pop = (int (*)())dlsym(h, "roctxRangePop");
+    if (!x.push || !x.pop) x = Roctx{};
+    return x;
+  }();
+  return r;
+}
+
+struct RoctxRange {
+  bool on;
+  RoctxRange(int stage0, int stages, int64_t n) : on(roctx().push != nullptr) {
+    if (!on) return;
+    char buf[96];
+    snprintf(buf, sizeof buf, "ksort passes %d..%d (n=%lld)", stage0, stage0 + stages - 1, (long long)n);
+    roctx().push(buf);
+  }
+  ~RoctxRange() {
+    if (on) roctx().pop();
+  }
+};
 int64_t next_call_id() { return g_call.fetch_add(1); }
 
 // ---------------------------------------------------------------- graphs
@@ -648,7 +707,7 @@ static int sort_in(Workspace& ws, const Variant& vv, const DeviceInfo& dinfo, in
   int rc = ws.reserve(caps, (size_t)std::max<int64_t>(n, 1) * v->key_bytes);
   if (rc) return rc;
   const int grid = stage_grid(*v, *di, ws.caps);
-  const bool prof = allow_profiling && profiling_on();
+  const bool prof = allow_profiling && (profiling_on() || tracing_on());
   ws.stats = prof;
   ws.epoch_span = epoch_span_setting();
   const int64_t call = next_call_id();
@@ -735,6 +794,7 @@ static int sort_in(Workspace& ws, const Variant& vv, const DeviceInfo& dinfo, in
       graphed = false;  // flags were read back by the graph
     } else {
      {
+      RoctxRange range(stage, batch, n);
       OrderedLaunches order(dev, stream);
       if (order.status()) return order.status();
       for (int b = 0; b < batch; ++b, ++stage) {

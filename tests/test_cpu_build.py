@@ -76,3 +76,18 @@ def test_server_with_async_queues_on_the_host_build(sim_build, hwq, slots):
 def test_exact_arrangement_on_the_host_build(sim_build, n, kinds):
     out = run(sim_build["exact_sim"], [n, kinds], {})
     assert "MISMATCH" not in out and "0 failed" in out
+
+
+def test_trace_file_on_the_host_build(sim_build, tmp_path):
+    """KSORT_TRACE: one JSON line per level pass of every sorting call; the
+    first pass partitions the whole array, and every pass of the call
+    carries the variant that ran."""
+    import json
+    path = tmp_path / "trace.jsonl"
+    n = 70_000
+    assert "ok" in run(sim_build["plain_sim"], [n], {"KSORT_TRACE": str(path)})
+    recs = [json.loads(x) for x in path.read_text().splitlines()]
+    assert len(recs) >= 3
+    assert recs[0]["stage"] == 0 and recs[0]["live_keys"] == n and recs[0]["dtype"] == "f64"
+    assert [r["stage"] for r in recs] == list(range(len(recs)))
+    assert len({(r["call"], r["block"], r["items"], r["cutoff"]) for r in recs}) == 1
