@@ -237,6 +237,8 @@ def batched_leg(ksort, torch) -> dict:
     torch.cuda.synchronize()
 
     def timed(first: int) -> float:
+        for c in copies[first:first + reps + 1]:
+            c.copy_(src)
         ksort.ksort_segmented(copies[first], d_offs, want_pivots=False)  # records the graph
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -247,13 +249,21 @@ def batched_leg(ksort, torch) -> dict:
 
     ksort.ksort_tune_file(None)  # untuned defaults
     default_variant = ksort.ksort_get_default(ksort.KSORT_F64)
-    seg_default_s = timed(0)
     tune_path = os.path.join(tempfile.mkdtemp(prefix="ksort_tune_"), "tune.json")
     ksort.ksort_tune_file(tune_path)
     tuned = ksort.ksort_autotune_batch(src, d_offs)
     with open(tune_path) as f:
         tune_json = json.load(f)
-    seg_s = timed(reps + 1)
+    # the untuned default and the tuned choice timed in turn, three times
+    # each (medians), so that drift between the two timings cancels
+    t_default, t_tuned = [], []
+    for _ in range(3):
+        ksort.ksort_tune_file(None)
+        t_default.append(timed(0))
+        ksort.ksort_tune_file(tune_path)
+        t_tuned.append(timed(reps + 1))
+    seg_default_s = sorted(t_default)[1]
+    seg_s = sorted(t_tuned)[1]
     # correctness: stable sort by key, then stable sort by array index
     seg_id = torch.repeat_interleave(torch.arange(4096, device="cuda"), d_offs[1:] - d_offs[:-1])
     v, idx = torch.sort(ref, stable=True)
@@ -282,6 +292,7 @@ def batched_leg(ksort, torch) -> dict:
     return {"arrays": 4096, "keys": n, "segmented_keys_per_s": n / seg_s, "segmented_ms": seg_s * 1e3,
             "tuned_variant": list(tuned), "default_variant": list(default_variant),
             "segmented_default_ms": seg_default_s * 1e3, "tuned_gain": seg_default_s / seg_s,
+            "tuned_is_default": list(tuned) == list(default_variant),
             "tune_file_entries": tune_json["entries"],
             "plain_loop_keys_per_s": n / loop_s, "plain_loop_ms": loop_s * 1e3,
             "one_plain_sort_keys_per_s": n / one_s, "one_plain_sort_ms": one_s * 1e3,
