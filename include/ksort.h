@@ -53,6 +53,13 @@
  *     kernels beside the sorts or run them under a counter profiler; it costs
  *     about 14 % at 7e6 keys and 0.5 % at 2^28 (512 claims per pass on one
  *     counter).
+ *   - KSORT_VALIDATE=1 (read per call) makes ksort_f64, ksort_f32,
+ *     ksort_sort_ex and ksort_segmented first check the whole input buffer
+ *     for the inputs outside the bit-exact contract (a NaN, or both +0.0 and
+ *     -0.0) and fail with KSORT_EINVAL, no key moved, if it finds one.  It
+ *     costs one read of the keys, a small device allocation and a stream
+ *     synchronization per call; the server and ksort_sort_static do not
+ *     check.
  */
 #ifndef KSORT_H
 #define KSORT_H

@@ -665,6 +665,67 @@ static int sort_in(Workspace& ws, const Variant& v, const DeviceInfo& di, int dt
                    const int64_t* d_offsets, int64_t nseg, int64_t* d_pivots, hipStream_t stream, bool use_graph,
                    bool allow_profiling);
 
+// ---------------------------------------------------------------- contract check
+//
+// The sort's output is the unique ascending arrangement, bit for bit, when
+// the keys hold no NaN and not both zeros (+0.0 and -0.0 compare equal, so
+// their relative order depends on the algorithm).  With KSORT_VALIDATE=1
+// the sorting calls check that first and refuse other inputs.
+
+// flags[0]: a NaN, flags[1]: a +0.0, flags[2]: a -0.0 (one atomic per wave
+// that found any)
+__device__ __forceinline__ bool sign_set(double v) { return __double_as_longlong(v) < 0; }
+__device__ __forceinline__ bool sign_set(float v) { return __float_as_int(v) < 0; }
+
+template <typename T>
+__global__ void contract_kernel(const T* d, int64_t n, int32_t* flags) {
+  bool nan = false, pz = false, nz = false;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const T v = d[x];
+    nan = nan || v != v;
+    if (v == T(0)) {
+      if (sign_set(v))
+        nz = true;
+      else
+        pz = true;
+    }
+  }
+  const uint64_t bn = __ballot(nan), bp = __ballot(pz), bz = __ballot(nz);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    if (bn) atomicOr(flags, 1);
+    if (bp) atomicOr(flags + 1, 1);
+    if (bz) atomicOr(flags + 2, 1);
+  }
+}
+
+static bool validating() {
+  const char* e = getenv("KSORT_VALIDATE");
+  return e && e[0] == '1' && e[1] == '\0';
+}
+
+static int check_contract(int dtype, const void* d, int64_t n, hipStream_t st) {
+  if (n <= 0) return KSORT_OK;
+  int32_t* dflags = nullptr;  // a debugging aid: one small allocation per call
+  KSORT_HIP(hipMalloc((void**)&dflags, 3 * sizeof(int32_t)));
+  int32_t h[3] = {0, 0, 0};
+  hipError_t e = hipMemsetAsync(dflags, 0, sizeof h, st);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
+  if (e == hipSuccess) {
+    if (dtype == KSORT_F64)
+      hipLaunchKernelGGL(contract_kernel<double>, dim3(grid), dim3(256), 0, st, (const double*)d, n, dflags);
+    else
+      hipLaunchKernelGGL(contract_kernel<float>, dim3(grid), dim3(256), 0, st, (const float*)d, n, dflags);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h, dflags, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(dflags);
+  if (e != hipSuccess) return hip_fail(e, "contract check");
+  if (h[0]) return fail(KSORT_EINVAL, "KSORT_VALIDATE: the keys hold a NaN (outside the bit-exact contract)");
+  if (h[1] && h[2]) return fail(KSORT_EINVAL, "KSORT_VALIDATE: the keys hold both +0.0 and -0.0 (outside the bit-exact contract)");
+  return KSORT_OK;
+}
+
 int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64_t nseg, int64_t* d_pivots,
              const ksort_tuning* tune, hipStream_t stream, bool use_graph) {
   if (dtype != KSORT_F64 && dtype != KSORT_F32) return fail(KSORT_EINVAL, "bad dtype");
@@ -675,6 +736,10 @@ int run_sort(int dtype, void* d_data, int64_t n, const int64_t* d_offsets, int64
   const Variant* v = find_variant(dtype, tune, n, d_offsets ? kTuneBatch : kTuneSingle);
   if (!v) return fail(KSORT_EINVAL, "no such kernel variant");
   if (nseg == 0) return KSORT_OK;
+  if (validating()) {
+    const int vrc = check_contract(dtype, d_data, n, stream);
+    if (vrc) return vrc;
+  }
   if (d_offsets == nullptr && n <= 1) {
     if (d_pivots) {
       const int64_t fp = n == 0 ? -1 : 0;

@@ -252,3 +252,31 @@ def test_stream_copy(ks):
     big = torch.zeros(1024, dtype=torch.uint8, device="cuda")
     with pytest.raises(ks.KsortError):
         ks.ksort_stream_copy(big[1:17], big[32:48])  # not 16-byte aligned
+
+
+def test_validate_refuses_inputs_outside_the_contract(ks, monkeypatch):
+    # KSORT_VALIDATE=1: a NaN, or both zeros, make the call fail with
+    # KSORT_EINVAL before any key moves; other inputs sort as usual.
+    torch = torch_dev()
+    monkeypatch.setenv("KSORT_VALIDATE", "1")
+    for dt in (torch.float64, torch.float32):
+        base = synth.torch_fill("uniform_f64", 41, 100_000, "cuda").to(dt)
+        for what, pos, val in (("nan", 77_777, float("nan")), ("both zeros", None, None)):
+            t = base.clone()
+            if what == "nan":
+                t[pos] = val
+            else:
+                t[10] = 0.0
+                t[20] = -0.0
+            keep = t.clone()
+            note(f"validate {what} {dt}")
+            with pytest.raises(ks.KsortError) as ei:
+                ks.sort_(t)
+            assert ei.value.code == -1 and "KSORT_VALIDATE" in str(ei.value)
+            assert torch.equal(t.view(torch.int64 if dt == torch.float64 else torch.int32),
+                               keep.view(torch.int64 if dt == torch.float64 else torch.int32))
+        t = base.clone()
+        t[5] = -0.0  # one kind of zero only: inside the contract
+        ks.sort_(t)
+        assert torch.equal(t, torch.sort(base.clone().index_fill_(0, torch.tensor([5], device="cuda"), -0.0))[0])
+    monkeypatch.delenv("KSORT_VALIDATE")
