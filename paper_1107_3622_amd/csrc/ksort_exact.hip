@@ -89,6 +89,13 @@ struct LevelArgs {
   const uint8_t* act;
   const uint8_t* act_prev;
   uint8_t* act_next;
+  // sort mode: the blocks that are not idle this level (see block_idle),
+  // listed by scan_level in claim order, and their number, by level parity;
+  // move_kernel and pair_kernel walk quarter blocks of this list only.
+  // Each count has a cache line of its own: one is cleared with a plain
+  // store while the other takes atomic adds.  Null in level mode.
+  int32_t* blist[2];
+  int32_t* nblist[2];
   // sort mode: sides of 2 .. kShort keys filed this level as (left, len),
   // in ngroups lists of small_cap entries each, one per group of
   // consecutive pair_kernel workgroups (npair of them), with the lengths in
@@ -114,6 +121,19 @@ template <typename T>
 __device__ __forceinline__ bool block_idle(const LevelArgs<T>& a, int64_t b) {
   return a.act && !a.act[b] && !a.act_prev[b];
 }
+
+// Reads the block list or its count, written by the kernel before, with
+// an agent-scope load, as the list was written (the address is the same in
+// every lane, and a plain load of it may be made a scalar load).
+__device__ __forceinline__ int32_t list_load(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Work unit of move_kernel and pair_kernel in sort mode: a quarter of a
+// listed block, kUnit / kThreads rounds of the workgroup.  Idle blocks are
+// not listed, so nearly idle levels cost little more than their launches.
+constexpr int kUnit = kSpan / 4;
+static_assert(kUnit % kThreads == 0, "whole rounds per unit");
 
 // (flag, sum) pairs: a flag starts a new run; sum counts smaller keys.
 struct Run {
@@ -201,8 +221,23 @@ __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
     if (c == 0) {
       a.sctr[a.par ^ 1] = 0;
       if (a.active) *a.active = 0;
+      if (a.nblist[0]) *a.nblist[a.par ^ 1] = 0;  // the next level's list
       if (a.nsmall)
         for (int g = 0; g < a.ngroups; ++g) a.nsmall[g] = 0;  // (one thread: at most kSmallGroups stores)
+    }
+    if (a.nblist[0]) {
+      // list the chunk's blocks that are not idle (one atomic per chunk;
+      // a bit mask, not an array indexed by a running count, which the
+      // device compiler was seen to fill wrongly here)
+      uint32_t m = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (c * K + k < a.nblocks && !block_idle(a, c * K + k)) m |= 1u << k;
+      if (m) {
+        int32_t at = atomicAdd(a.nblist[a.par], __builtin_popcount(m));
+        for (int k = 0; k < K; ++k)
+          if ((m >> k) & 1) __hip_atomic_store(a.blist[a.par] + at++, (int32_t)(c * K + k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
   __syncthreads();
@@ -249,6 +284,20 @@ __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
         lbits[k] |= (uint32_t)p.s << j;
       }
     }
+  }
+  bool any_live = false;
+#pragma unroll
+  for (int k = 0; k < K; ++k) any_live = any_live || live[k];
+  if (!any_live) {
+    // every block of the chunk is a run start counting nothing whatever
+    // comes before it: its run from the array's start is its own, published
+    // at once; nothing reads its counts
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (b0 + k < a.nblocks)
+          __hip_atomic_store(st + b0 + k, run_word(kRunIncl, Run{1, 0}), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
   }
   block_scan_k<K>(r, sf, ss);
   if (threadIdx.x < 64) {
@@ -352,44 +401,60 @@ __device__ __forceinline__ Call<T> call_of(const LevelArgs<T>& a, int32_t h) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void move_kernel(LevelArgs<T> a) {
-  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < a.n; x += (int64_t)gridDim.x * kThreads) {
-    if (block_idle(a, x / kSpan)) continue;
-    const int32_t h = a.hd[x];
-    if (h < 0) {
-      // a key that became final in the level before is copied once; both
-      // buffers hold it from then on (hd2 still holds that level's state)
-      if (a.sort_mode && (!a.act || a.hd2[x] >= 0)) a.nxt[x] = a.cur[x];
-      continue;
-    }
-    const Call<T> k = call_of(a, h);
-    if (x == k.left) {
-      a.nxt[k.i] = k.key;
-      continue;
-    }
-    const T v = a.cur[x];
-    const bool lt = !(k.key <= v);
-    if (x <= k.m) {
-      if (lt) {
-        a.nxt[x - 1] = v;
-      } else {
-        const int64_t r = (x - k.left) - a.ltp[x];  // rank among the keys >= key in (left, x]
-        if (r == 1)
-          a.nxt[k.i + 1] = v;
-        else
-          a.qkey[k.left + r] = v;
-        a.qpos[k.left + r] = (int32_t)x;
-      }
+__device__ __forceinline__ void move_one(const LevelArgs<T>& a, int64_t x) {
+  const int32_t h = a.hd[x];
+  if (h < 0) {
+    // a key that became final in the level before is copied once; both
+    // buffers hold it from then on (hd2 still holds that level's state)
+    if (a.sort_mode && (!a.act || a.hd2[x] >= 0)) a.nxt[x] = a.cur[x];
+    return;
+  }
+  const Call<T> k = call_of(a, h);
+  if (x == k.left) {
+    a.nxt[k.i] = k.key;
+    return;
+  }
+  const T v = a.cur[x];
+  const bool lt = !(k.key <= v);
+  if (x <= k.m) {
+    if (lt) {
+      a.nxt[x - 1] = v;
     } else {
-      if (!lt) {
-        a.nxt[x] = v;
-      } else {
-        const int64_t r = k.c - a.ltp[x] + 1;  // rank among the smaller keys in [x, right]
-        a.rpos[k.left + r] = (int32_t)x;
-        a.rkey[k.left + r] = v;
-      }
+      const int64_t r = (x - k.left) - a.ltp[x];  // rank among the keys >= key in (left, x]
+      if (r == 1)
+        a.nxt[k.i + 1] = v;
+      else
+        a.qkey[k.left + r] = v;
+      a.qpos[k.left + r] = (int32_t)x;
+    }
+  } else {
+    if (!lt) {
+      a.nxt[x] = v;
+    } else {
+      const int64_t r = k.c - a.ltp[x] + 1;  // rank among the smaller keys in [x, right]
+      a.rpos[k.left + r] = (int32_t)x;
+      a.rkey[k.left + r] = v;
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void move_kernel(LevelArgs<T> a) {
+  if (a.nblist[0]) {
+    const int64_t nu = 4 * (int64_t)list_load(a.nblist[a.par]);
+    const int32_t* bl = a.blist[a.par];
+    for (int64_t u = blockIdx.x; u < nu; u += gridDim.x) {
+      const int64_t base = (int64_t)list_load(bl + (u >> 2)) * kSpan + (u & 3) * kUnit;
+#pragma unroll
+      for (int j = 0; j < kUnit / kThreads; ++j) {
+        const int64_t x = base + j * kThreads + threadIdx.x;
+        if (x < a.n) move_one(a, x);
+      }
+    }
+    return;
+  }
+  for (int64_t x = (int64_t)blockIdx.x * kThreads + threadIdx.x; x < a.n; x += (int64_t)gridDim.x * kThreads)
+    if (!block_idle(a, x / kSpan)) move_one(a, x);
 }
 
 template <typename T>
@@ -399,11 +464,11 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
   const int lane = threadIdx.x & 63;
   // this workgroup's list of short sides (sort mode)
   const int32_t grp = a.small ? (int32_t)((int64_t)blockIdx.x * a.ngroups / a.npair) : 0;
-  // Every thread of a workgroup runs the same iterations (the bound is on
-  // the workgroup's first position) and the waves file their short sides on
-  // their own, so nothing in the loop waits for the other waves.
-  for (int64_t base = (int64_t)blockIdx.x * kThreads; base < a.n; base += (int64_t)gridDim.x * kThreads) {
-    if (block_idle(a, base / kSpan)) continue;  // the same span block for the whole workgroup
+  // One round: the kThreads positions from base.  Every thread of a
+  // workgroup runs the same rounds (the bounds are on the round's first
+  // position) and the waves file their short sides on their own, so nothing
+  // in a round waits for the other waves.
+  auto round = [&](int64_t base) {
     const int64_t x = base + threadIdx.x;
     bool file = false;
     int2 entry{0, 0};
@@ -480,14 +545,26 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
       // atomic per wave with sides to file; no workgroup barrier)
       const uint64_t fm = __ballot(file);
       if (fm) {
-        int32_t base = 0;
-        if (lane == 0) base = atomicAdd(a.nsmall + grp, (int32_t)__popcll(fm));
-        base = __shfl(base, 0);
+        int32_t at = 0;
+        if (lane == 0) at = atomicAdd(a.nsmall + grp, (int32_t)__popcll(fm));
+        at = __shfl(at, 0);
         if (file)
-          a.small[grp * a.small_cap + base +
+          a.small[grp * a.small_cap + at +
                   __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0))] = entry;
       }
     }
+  };
+  if (a.nblist[0]) {
+    const int64_t nu = 4 * (int64_t)list_load(a.nblist[a.par]);
+    const int32_t* bl = a.blist[a.par];
+    for (int64_t u = blockIdx.x; u < nu; u += gridDim.x) {
+      const int64_t b0 = (int64_t)list_load(bl + (u >> 2)) * kSpan + (u & 3) * kUnit;
+      for (int j = 0; j < kUnit / kThreads; ++j)
+        if (b0 + j * kThreads < a.n) round(b0 + j * kThreads);
+    }
+  } else {
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < a.n; base += (int64_t)gridDim.x * kThreads)
+      if (!block_idle(a, base / kSpan)) round(base);  // the same span block for the whole workgroup
   }
   // The next level runs while any position is in a segment of two or more
   // keys: a flag, set with plain stores.  Calls are counted per workgroup.
@@ -808,10 +885,12 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
   a.npair = grid_for(n);
   a.ngroups = std::min(kSmallGroups, a.npair);
   {
-    // a workgroup's iterations of kThreads positions each file at most
-    // kThreads / 2 sides (disjoint, two keys or more); a group holds at most
-    // ceil(npair / ngroups) workgroups
-    const int64_t iters = (n + (int64_t)a.npair * kThreads - 1) / ((int64_t)a.npair * kThreads);
+    // a workgroup's rounds of kThreads positions each file at most
+    // kThreads / 2 sides (disjoint, two keys or more); it takes at most
+    // ceil(4 * blocks / npair) units of kUnit / kThreads rounds, and a group
+    // holds at most ceil(npair / ngroups) workgroups
+    const int64_t nb = (n + kSpan - 1) / kSpan;
+    const int64_t iters = (4 * nb + a.npair - 1) / a.npair * (kUnit / kThreads);
     a.small_cap = ((int64_t)a.npair + a.ngroups - 1) / a.ngroups * iters * (kThreads / 2) + 1;
   }
   auto layout = [&](Carve& B) {
@@ -820,6 +899,9 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
     if (!r) r = B.take(&act_ring, (size_t)3 * a.nblocks);
     if (!r) r = B.take(&a.small, (size_t)a.ngroups * a.small_cap);
     if (!r) r = B.take(&a.nsmall, (size_t)a.ngroups);
+    if (!r) r = B.take(&a.blist[0], (size_t)2 * a.nblocks);
+    if (!r) r = B.take(&a.nblist[0], 1);  // (every piece starts a 256-byte line)
+    if (!r) r = B.take(&a.nblist[1], 1);
     if (!r && count_per_group) r = B.take(&a.wcalls, (size_t)(kPairGrid + kSmallGrid));
     return r;
   };
@@ -831,6 +913,9 @@ static int sort_exact(T* data, int64_t n, int64_t* d_first_pivot, int64_t* d_cal
   if ((rc = layout(B))) return rc;
   unsigned long long* h_active = A->h;
   KSORT_HIP(hipMemsetAsync(act_ring, 1, (size_t)3 * a.nblocks, st));
+  a.blist[1] = a.blist[0] + a.nblocks;
+  KSORT_HIP(hipMemsetAsync(a.nblist[0], 0, sizeof(int32_t), st));
+  KSORT_HIP(hipMemsetAsync(a.nblist[1], 0, sizeof(int32_t), st));
   a.sort_mode = 1;
   a.calls = d_calls;
   a.calls_cap = d_calls ? calls_cap : 0;
