@@ -256,34 +256,6 @@ __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
       a.sstat[a.par ^ 1][blk] = 0;  // the next level's word starts unpublished
       if (a.act) a.act_next[blk] = 0;
     }
-    if (!live[k]) continue;
-    r[k] = Run{0, 0};
-    const int64_t base = blk * kSpan + (int64_t)threadIdx.x * kItems;
-    if (base + kItems <= a.n) {
-      int32_t h[kItems];
-      T v[kItems];
-#pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        h[j] = a.hd[base + j];
-        v[j] = a.cur[base + j];
-      }
-#pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        const bool start = h[j] < 0 || h[j] == base + j;
-        const bool lt = !start && !(a.cur[h[j]] <= v[j]);
-        r[k] = join(r[k], Run{start ? 1 : 0, lt ? 1 : 0});
-        fbits[k] |= (uint32_t)start << j;
-        lbits[k] |= (uint32_t)lt << j;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        const Run p = pos_run(a, base + j);
-        r[k] = join(r[k], p);
-        fbits[k] |= (uint32_t)p.f << j;
-        lbits[k] |= (uint32_t)p.s << j;
-      }
-    }
   }
   bool any_live = false;
 #pragma unroll
@@ -298,6 +270,64 @@ __global__ __launch_bounds__(kThreads) void scan_level(LevelArgs<T> a) {
         if (b0 + k < a.nblocks)
           __hip_atomic_store(st + b0 + k, run_word(kRunIncl, Run{1, 0}), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return;
+  }
+  // The positions are read striped (item j of every thread at j * kThreads
+  // + t, so each load of a wave covers consecutive positions), and each
+  // position's two bits reach the thread that scans it (kItems consecutive
+  // positions from t * kItems) through the waves' ballots, kept in LDS.
+  static_assert(kItems == 16 && kThreads == 256, "the bit exchange below assumes 16 rows of 256 positions");
+  __shared__ uint64_t s_fm[K][kItems][kThreads / 64], s_lm[K][kItems][kThreads / 64];
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!live[k]) continue;
+      const int64_t base = (b0 + k) * kSpan + threadIdx.x;
+      if ((b0 + k + 1) * kSpan <= a.n) {
+        int32_t h[kItems];
+        T v[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+          h[j] = a.hd[base + j * kThreads];
+          v[j] = a.cur[base + j * kThreads];
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+          const bool start = h[j] < 0 || h[j] == base + j * kThreads;
+          const bool lt = !start && !(a.cur[h[j]] <= v[j]);
+          const uint64_t fm = __ballot(start), lm = __ballot(lt);
+          if (lane == 0) {
+            s_fm[k][j][wv] = fm;
+            s_lm[k][j][wv] = lm;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+          const Run p = pos_run(a, base + j * kThreads);
+          const uint64_t fm = __ballot(p.f != 0), lm = __ballot(p.s != 0);
+          if (lane == 0) {
+            s_fm[k][j][wv] = fm;
+            s_lm[k][j][wv] = lm;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  {
+    // thread t's positions t * 16 .. t * 16 + 15: row t / 16, wave
+    // (t % 16) / 4 of that row, bits (t % 4) * 16 ..
+    const int t = threadIdx.x, row = t >> 4, w = (t & 15) >> 2, sh = (t & 3) * 16;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (!live[k]) continue;
+      fbits[k] = (uint32_t)(s_fm[k][row][w] >> sh) & 0xffffu;
+      lbits[k] = (uint32_t)(s_lm[k][row][w] >> sh) & 0xffffu;
+      r[k] = Run{0, 0};
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) r[k] = join(r[k], Run{(int)((fbits[k] >> j) & 1), (int)((lbits[k] >> j) & 1)});
+    }
   }
   block_scan_k<K>(r, sf, ss);
   if (threadIdx.x < 64) {
