@@ -430,27 +430,45 @@ __device__ __forceinline__ Call<T> call_of(const LevelArgs<T>& a, int32_t h) {
   return k;
 }
 
+// call_of for any position of a listed block: a final position (h < 0)
+// gets a call on itself, with every index kept inside the array, whose
+// numbers are never used.  So the loads of several rounds can all be
+// issued before any branch on them.  For h >= 0 it equals call_of.
+__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : v > hi ? hi : v; }
 template <typename T>
-__device__ __forceinline__ void move_one(const LevelArgs<T>& a, int64_t x) {
-  const int32_t h = a.hd[x];
+__device__ __forceinline__ Call<T> call_any(const LevelArgs<T>& a, int32_t h, int64_t x) {
+  Call<T> k;
+  const int64_t last = a.n - 1;
+  k.left = h < 0 ? x : h;
+  k.right = clamp64(k.left + (int64_t)a.ln[k.left] - 1, k.left, last);
+  k.key = a.cur[k.left];
+  k.c = a.ltp[k.right];
+  k.i = clamp64(k.left + k.c, k.left, k.right);
+  const T after = a.cur[k.i < last ? k.i + 1 : last];
+  k.m = (k.i < k.right && k.key <= after) ? k.i + 1 : k.i;
+  return k;
+}
+
+// The moves of position x in segment h (h >= 0) with call k: v = cur[x],
+// lp = ltp[x].  For a final position (h < 0, sort mode) lp is hd2[x]: the
+// key is copied if it was in a segment the level before.
+template <typename T>
+__device__ __forceinline__ void move_apply(const LevelArgs<T>& a, int64_t x, int32_t h, const Call<T>& k, T v,
+                                           int32_t lp) {
   if (h < 0) {
-    // a key that became final in the level before is copied once; both
-    // buffers hold it from then on (hd2 still holds that level's state)
-    if (a.sort_mode && (!a.act || a.hd2[x] >= 0)) a.nxt[x] = a.cur[x];
+    if (lp >= 0) a.nxt[x] = v;
     return;
   }
-  const Call<T> k = call_of(a, h);
   if (x == k.left) {
     a.nxt[k.i] = k.key;
     return;
   }
-  const T v = a.cur[x];
   const bool lt = !(k.key <= v);
   if (x <= k.m) {
     if (lt) {
       a.nxt[x - 1] = v;
     } else {
-      const int64_t r = (x - k.left) - a.ltp[x];  // rank among the keys >= key in (left, x]
+      const int64_t r = (x - k.left) - lp;  // rank among the keys >= key in (left, x]
       if (r == 1)
         a.nxt[k.i + 1] = v;
       else
@@ -461,11 +479,23 @@ __device__ __forceinline__ void move_one(const LevelArgs<T>& a, int64_t x) {
     if (!lt) {
       a.nxt[x] = v;
     } else {
-      const int64_t r = k.c - a.ltp[x] + 1;  // rank among the smaller keys in [x, right]
+      const int64_t r = k.c - lp + 1;  // rank among the smaller keys in [x, right]
       a.rpos[k.left + r] = (int32_t)x;
       a.rkey[k.left + r] = v;
     }
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void move_one(const LevelArgs<T>& a, int64_t x) {
+  const int32_t h = a.hd[x];
+  if (h < 0) {
+    // a key that became final in the level before is copied once; both
+    // buffers hold it from then on (hd2 still holds that level's state)
+    if (a.sort_mode && (!a.act || a.hd2[x] >= 0)) a.nxt[x] = a.cur[x];
+    return;
+  }
+  move_apply(a, x, h, call_of(a, h), a.cur[x], a.ltp[x]);
 }
 
 template <typename T>
@@ -475,11 +505,28 @@ __global__ __launch_bounds__(kThreads) void move_kernel(LevelArgs<T> a) {
     const int32_t* bl = a.blist[a.par];
     for (int64_t u = blockIdx.x; u < nu; u += gridDim.x) {
       const int64_t base = (int64_t)list_load(bl + (u >> 2)) * kSpan + (u & 3) * kUnit;
+      // the unit's rounds load everything first (their chains of dependent
+      // loads overlap), then store
+      constexpr int R = kUnit / kThreads;
+      int64_t xs[R];
+      int32_t hs[R], lps[R];
+      T vs[R];
+      Call<T> ks[R];
 #pragma unroll
-      for (int j = 0; j < kUnit / kThreads; ++j) {
-        const int64_t x = base + j * kThreads + threadIdx.x;
-        if (x < a.n) move_one(a, x);
+      for (int j = 0; j < R; ++j) {
+        xs[j] = base + j * kThreads + threadIdx.x;
+        hs[j] = a.hd[xs[j] < a.n ? xs[j] : a.n - 1];
       }
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int64_t xc = xs[j] < a.n ? xs[j] : a.n - 1;
+        ks[j] = call_any(a, hs[j], xc);
+        vs[j] = a.cur[xc];
+        lps[j] = (hs[j] < 0 ? a.hd2 : a.ltp)[xc];  // (sort mode: hd2 is there)
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if (xs[j] < a.n) move_apply(a, xs[j], hs[j], ks[j], vs[j], lps[j]);
     }
     return;
   }
@@ -498,18 +545,17 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
   // workgroup runs the same rounds (the bounds are on the round's first
   // position) and the waves file their short sides on their own, so nothing
   // in a round waits for the other waves.
-  auto round = [&](int64_t base) {
+  // h, k and lm (= ltp[k.m]) are the round's position's loads (call_any).
+  auto round = [&](int64_t base, int32_t h, const Call<T>& k, int32_t lm) {
     const int64_t x = base + threadIdx.x;
     bool file = false;
     int2 entry{0, 0};
     if (x < a.n) {
-      const int32_t h = a.hd[x];
       if (h < 0) {
         if (a.sort_mode) a.hd2[x] = -1;
       } else {
-        const Call<T> k = call_of(a, h);
-        const int64_t nq = (k.m - k.left) - a.ltp[k.m];  // keys >= key in (left, m]
-        const int64_t nr = k.c - a.ltp[k.m];             // smaller keys in (m, right]
+        const int64_t nq = (k.m - k.left) - lm;  // keys >= key in (left, m]
+        const int64_t nr = k.c - lm;             // smaller keys in (m, right]
         const int64_t r = x - k.left;
         // (the slots read here were filed by move_kernel in this level: the
         // closed form has nr = nq or nq - 1; the range checks only keep a
@@ -589,12 +635,33 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(LevelArgs<T> a) {
     const int32_t* bl = a.blist[a.par];
     for (int64_t u = blockIdx.x; u < nu; u += gridDim.x) {
       const int64_t b0 = (int64_t)list_load(bl + (u >> 2)) * kSpan + (u & 3) * kUnit;
-      for (int j = 0; j < kUnit / kThreads; ++j)
-        if (b0 + j * kThreads < a.n) round(b0 + j * kThreads);
+      // every round's chain of loads first, so that they overlap
+      constexpr int R = kUnit / kThreads;
+      int32_t hs[R], lms[R];
+      Call<T> ks[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int64_t x = b0 + j * kThreads + threadIdx.x;
+        hs[j] = a.hd[x < a.n ? x : a.n - 1];
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int64_t x = b0 + j * kThreads + threadIdx.x;
+        ks[j] = call_any(a, hs[j], x < a.n ? x : a.n - 1);
+        lms[j] = a.ltp[ks[j].m];
+      }
+#pragma unroll
+      for (int j = 0; j < R; ++j)
+        if (b0 + j * kThreads < a.n) round(b0 + j * kThreads, hs[j], ks[j], lms[j]);
     }
   } else {
-    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < a.n; base += (int64_t)gridDim.x * kThreads)
-      if (!block_idle(a, base / kSpan)) round(base);  // the same span block for the whole workgroup
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < a.n; base += (int64_t)gridDim.x * kThreads) {
+      if (block_idle(a, base / kSpan)) continue;  // the same span block for the whole workgroup
+      const int64_t xc = base + threadIdx.x < a.n ? base + threadIdx.x : a.n - 1;
+      const int32_t h = a.hd[xc];
+      const Call<T> k = call_any(a, h, xc);
+      round(base, h, k, a.ltp[k.m]);
+    }
   }
   // The next level runs while any position is in a segment of two or more
   // keys: a flag, set with plain stores.  Calls are counted per workgroup.
