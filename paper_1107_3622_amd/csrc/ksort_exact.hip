@@ -19,10 +19,13 @@
 //
 // Everything follows from one number per position: the count of smaller
 // keys from its segment's start up to it (a segmented scan).  A level is
-//   scan_level  : that count, in ltp[] (one pass, decoupled look-back);
+//   scan_level  : that count, in ltp[] (one pass, decoupled look-back), and
+//                 in a whole sort the list of blocks not idle this level;
 //   move_kernel : keys that shift or stay, and the q and r keys filed by rank;
 //   pair_kernel : q_k -> r_{k-1} and r_k -> q_k - 1, the call record, and the
-//                 segments of the next level (Steps 5-6).
+//                 segments of the next level (Steps 5-6);
+//   small_kernel: in a whole sort, every remaining call on the sides of at
+//                 most 64 keys, one wave per side.
 // Per position the state is hd[x], the first position of its segment (-1 if
 // the key is final or outside every segment), and, at a segment's first
 // position, ln[x], its length.  Positions are 32-bit: n < 2^31.
